@@ -311,9 +311,9 @@ std::vector<C<T>> convolve(const std::vector<uint32_t> &x,
 // report an error if it holds several; section 2.5).  For i < L the real part
 // must contain exactly one integer: ceil(lo) == floor(hi).  Two ceil(lo) <
 // floor(hi) means several integers: "enclosure too wide".  ceil(lo) > floor(hi)
-// (no integer), a negative integer, or an imaginary part that excludes 0 cannot
-// happen for a rigorous enclosure of a non-negative integer, so it is reported
-// as an internal error.  The padded tail i >= L must contain 0 in both parts.
+// (no integer), a single integer that is negative, or an imaginary part that
+// excludes 0 cannot happen for a rigorous enclosure of a non-negative integer,
+// so it is reported as an internal error.  The padded tail i >= L must contain 0 in both parts.
 // mode 1 is the stricter variant that also fails any enclosure that contains a
 // half-integer.  Also reports max_i RU((hi - lo)/2) over i < L and the number of
 // real enclosures that contain a half-integer.
@@ -338,8 +338,9 @@ int certify(const std::vector<C<T>> &Z, size_t L, int mode, std::vector<int64_t>
     bool half = std::ceil(sub_dir(lo, 0.5, FE_DOWNWARD)) <= std::floor(sub_dir(hi, 0.5, FE_UPWARD));
     if (half) ++nhalf;
     double m = std::ceil(lo), M = std::floor(hi);
-    if (m > M || !im0 || m < 0) { st = ST_INTERNAL; continue; }
+    if (m > M || !im0) { st = ST_INTERNAL; continue; }
     if (m < M || (mode == 1 && half)) { if (st == ST_OK) st = ST_TOO_WIDE; continue; }
+    if (m < 0) { st = ST_INTERNAL; continue; }  // the one integer is negative
     (*c)[i] = static_cast<int64_t>(m);
   }
   *max_radius = rmax;

@@ -386,6 +386,7 @@ CERTIFY_CASES = [
     ((2.9, 4.1), oracle.ST_TOO_WIDE, None, 1),
     ((3.2, 3.8), oracle.ST_INTERNAL, None, 1),
     ((-1.2, -0.9), oracle.ST_INTERNAL, None, 0),
+    ((-1.3, 5.0), oracle.ST_TOO_WIDE, None, 1),
 ]
 
 
