@@ -1,0 +1,146 @@
+/*
+ * ssa.h -- C ABI of the MI355X (gfx950) rigorous complex-interval
+ * Schoenhage-Strassen integer multiplication library (libssa.so).
+ *
+ * The operation is the one stated in the paper's section 2 (Steinke &
+ * Sainudiin, CCA 2010): given x in Z_b^n and y in Z_b^m, little-endian digit
+ * vectors (value = sum x_i b^i), return z in Z_b^{n+m} with z = x * y.  The
+ * product is computed by the fast convolution of section 2.3 over rectangular
+ * complex intervals with outward rounding (section 2.5), and each convolution
+ * coefficient is taken as the unique integer in its enclosure; when an
+ * enclosure holds more than one integer the product is not returned and the
+ * status says so (section 1: "report an error").  A returned product is
+ * therefore exact (a computer-aided proof of the product), never approximate.
+ *
+ * Conventions for every entry point
+ *  - Operands and results are BYTES (base 256, little-endian).  digit_bits = 4
+ *    only changes the internal digit base (each byte is split into two base-16
+ *    digits, low nibble first); the interface stays in bytes.
+ *  - Pointers named a, b, out, status_dev, and the debug buffers are DEVICE
+ *    pointers (hipMalloc'd memory or tensors of the calling framework) owned by
+ *    the caller.  Host pointers are named *_host or are plain size arrays.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *  - The library never reads outside [a, a+na), [b, b+nb) and never writes
+ *    outside [out, out+na+nb).
+ *  - Return value: SSA_OK, or the error that prevented the call from running
+ *    (invalid argument, out of memory, device error).  The outcome of a product
+ *    (certified or not) is reported separately in its status.
+ *  - Thread safety: a plan is used by one host thread at a time.
+ */
+#ifndef SSA_H_
+#define SSA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SSA_OK = 0,                 /* product certified; out holds the exact na+nb bytes */
+  SSA_ENCLOSURE_TOO_WIDE = 1, /* some enclosure held >1 integer; out is all zeros   */
+  SSA_INVALID_ARGUMENT = 2,   /* null pointer, zero length, size above the plan's max */
+  SSA_OUT_OF_MEMORY = 3,      /* device or pinned host allocation failed             */
+  SSA_DEVICE_ERROR = 4,       /* a HIP call failed, or the carry scan gave up         */
+  SSA_INTERNAL_ERROR = 5      /* an enclosure excluded every integer: cannot happen
+                                 for rigorous arithmetic; out is all zeros           */
+} ssa_status;
+
+enum { SSA_FP64 = 0, SSA_FP32_FALLBACK = 1 };
+enum { SSA_CERTIFY_ONE_INTEGER = 0, SSA_CERTIFY_HALF_INTEGER = 1 };
+
+typedef struct {
+  int precision;           /* SSA_FP64 (the path of the paper)                         */
+  int digit_bits;          /* 8: base-256 digits (paper, section 3); 4: base 16        */
+  int certify_mode;        /* SSA_CERTIFY_ONE_INTEGER: exactly one integer (section 1);
+                              SSA_CERTIFY_HALF_INTEGER: additionally fail any enclosure
+                              that contains a half-integer (stricter)                 */
+  int reserved;
+} ssa_plan_opts;
+
+typedef struct {
+  double max_radius;   /* max over coefficients of the real-part half-width, rounded up */
+  uint64_t half_int;   /* coefficients whose enclosure contains a half-integer         */
+  uint32_t too_wide;   /* coefficients whose enclosure holds several integers          */
+  uint32_t internal;   /* enclosures that exclude every integer (must be 0)            */
+  uint32_t carry_err;  /* carry-scan waits that timed out (must be 0)                  */
+  uint32_t log_n;      /* transform length used, N = 2^log_n                           */
+  int status;          /* ssa_status of the product                                    */
+  int reserved;
+} ssa_stats;
+
+typedef struct ssa_plan ssa_plan;
+typedef struct ssa_batch ssa_batch;
+
+/* Transform length N = 2^k with k = ceil(log2(L)), L = digits(a) + digits(b) - 1
+ * (section 2.3, fast convolution box, generalised to unequal lengths); products
+ * with L <= 128 are padded to N = 256 (zero padding does not change them). */
+size_t ssa_fft_size(size_t na, size_t nb, int digit_bits);
+
+/* Create a plan for products with na <= max_na, nb <= max_nb bytes.  Allocates
+ * all device scratch once (ssa_mul never allocates), generates the certified
+ * twiddle table on the device (section 2.2 half-angle recurrence) and waits
+ * for it.  opts may be NULL (FP64, base 256, one-integer certification).
+ * On error *plan is NULL. */
+ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
+                           const ssa_plan_opts *opts, void *stream);
+
+/* Release a plan and everything it allocated.  NULL is ignored. */
+void ssa_plan_destroy(ssa_plan *plan);
+
+/* z = a * b.  a: na bytes, b: nb bytes, out: na + nb bytes (device).  Runs on
+ * the plan's stream and synchronises it; *status (host) receives the product's
+ * ssa_status.  On any status other than SSA_OK, out is zero-filled. */
+ssa_status ssa_mul(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
+                   uint8_t *out, ssa_status *status);
+
+/* Statistics of the last ssa_mul on this plan. */
+ssa_status ssa_get_stats(const ssa_plan *plan, ssa_stats *stats_host);
+
+/* Batches: `count` independent products of uneven lengths, each within the
+ * plan's max_na / max_nb.  The arrays a, na, b, nb, out are HOST arrays of
+ * device pointers and byte counts.  Creation validates every product,
+ * allocates the batch's device scratch (the batch owns it), groups the
+ * products by transform length, uploads the work descriptors and captures the
+ * whole launch sequence into one HIP graph. */
+ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *a,
+                            const size_t *na, const uint8_t *const *b, const size_t *nb,
+                            uint8_t *const *out, ssa_batch **batch);
+/* Run a batch (one graph launch, stream-ordered, no host synchronisation).
+ * status_dev: device array of `count` ints, receives each product's ssa_status. */
+ssa_status ssa_batch_run(ssa_batch *batch, int *status_dev);
+/* Per-product statistics of the last run (host array of `count`); synchronises. */
+ssa_status ssa_batch_stats(ssa_batch *batch, ssa_stats *stats_host);
+void ssa_batch_destroy(ssa_batch *batch);
+
+/* Convenience: create, run, synchronise, destroy. */
+ssa_status ssa_mul_batch(ssa_plan *plan, size_t count, const uint8_t *const *a, const size_t *na,
+                         const uint8_t *const *b, const size_t *nb, uint8_t *const *out,
+                         int *status_dev);
+
+/* ---- Diagnostics used by the test-suite ------------------------------------ */
+
+/* Same computation as ssa_mul, and also writes the final enclosures of all N
+ * convolution outputs (after the inverse transform and the 1/N factor, before
+ * certification) to enc_dev: N x 4 doubles {re_lo, re_hi, im_lo, im_hi}. */
+ssa_status ssa_debug_enclosures(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b,
+                                size_t nb, uint8_t *out, double *enc_dev, ssa_status *status);
+
+/* Copy the plan's twiddle table: Ntab x 2 doubles (cos, sin of 2 pi t / Ntab)
+ * to tab_dev, and its common error bound to *e_host.  Returns log2(Ntab) in
+ * *log_ntab_host. */
+ssa_status ssa_twiddle_table(const ssa_plan *plan, double *tab_dev, double *e_host,
+                             int *log_ntab_host);
+
+/* The device directed-rounding primitives on n inputs (device arrays):
+ * op 0 RU(a+b), 1 RU(a*b), 2 RU(a*b+c), 3 RD(a+b), 4 RD(a*b), 5 RD(a*b+c).
+ * Synchronises the stream. */
+ssa_status ssa_probe_directed(int op, const double *a, const double *b, const double *c,
+                              double *out, size_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSA_H_ */

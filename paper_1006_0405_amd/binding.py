@@ -1,0 +1,260 @@
+"""Python binding of libssa.so (include/ssa.h): argument marshalling only.
+
+Every step of the multiplication runs in the library's HIP kernels; this module
+passes device pointers of torch tensors (PyTorch serves as the device-memory and
+stream provider) and sizes through ctypes, and converts status codes.  If the
+library has not been built the import of the functions below raises: there is
+no other implementation to fall back to.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch  # loaded first: libssa.so then binds to the HIP runtime torch brought in
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libssa.so")
+
+SSA_OK = 0
+SSA_ENCLOSURE_TOO_WIDE = 1
+SSA_INVALID_ARGUMENT = 2
+SSA_OUT_OF_MEMORY = 3
+SSA_DEVICE_ERROR = 4
+SSA_INTERNAL_ERROR = 5
+STATUS_NAMES = {0: "OK", 1: "ENCLOSURE_TOO_WIDE", 2: "INVALID_ARGUMENT", 3: "OUT_OF_MEMORY",
+                4: "DEVICE_ERROR", 5: "INTERNAL_ERROR"}
+
+SSA_FP64 = 0
+SSA_CERTIFY_ONE_INTEGER = 0
+SSA_CERTIFY_HALF_INTEGER = 1
+
+# Every entry point declared in include/ssa.h.
+EXPORTS = ("ssa_fft_size", "ssa_plan_create", "ssa_plan_destroy", "ssa_mul", "ssa_get_stats",
+           "ssa_batch_create", "ssa_batch_run", "ssa_batch_stats", "ssa_batch_destroy",
+           "ssa_mul_batch", "ssa_debug_enclosures", "ssa_twiddle_table", "ssa_probe_directed")
+
+
+class SsaError(RuntimeError):
+    pass
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("digit_bits", ctypes.c_int),
+                ("certify_mode", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("max_radius", ctypes.c_double), ("half_int", ctypes.c_uint64),
+                ("too_wide", ctypes.c_uint32), ("internal", ctypes.c_uint32),
+                ("carry_err", ctypes.c_uint32), ("log_n", ctypes.c_uint32),
+                ("status", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+
+
+def lib():
+    """Load libssa.so; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SsaError("libssa.so is not built (%s); run __graft_entry__.build() or "
+                           "python paper_1006_0405_amd/build.py" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        L.ssa_fft_size.restype = _sz
+        L.ssa_fft_size.argtypes = [_sz, _sz, ctypes.c_int]
+        L.ssa_plan_create.restype = ctypes.c_int
+        L.ssa_plan_create.argtypes = [ctypes.POINTER(_vp), _sz, _sz, ctypes.POINTER(PlanOpts), _vp]
+        L.ssa_plan_destroy.restype = None
+        L.ssa_plan_destroy.argtypes = [_vp]
+        L.ssa_mul.restype = ctypes.c_int
+        L.ssa_mul.argtypes = [_vp, _vp, _sz, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_int)]
+        L.ssa_get_stats.restype = ctypes.c_int
+        L.ssa_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
+        L.ssa_batch_create.restype = ctypes.c_int
+        L.ssa_batch_create.argtypes = [_vp, _sz, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]
+        L.ssa_batch_run.restype = ctypes.c_int
+        L.ssa_batch_run.argtypes = [_vp, _vp]
+        L.ssa_batch_stats.restype = ctypes.c_int
+        L.ssa_batch_stats.argtypes = [_vp, _vp]
+        L.ssa_batch_destroy.restype = None
+        L.ssa_batch_destroy.argtypes = [_vp]
+        L.ssa_mul_batch.restype = ctypes.c_int
+        L.ssa_mul_batch.argtypes = [_vp, _sz, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.ssa_debug_enclosures.restype = ctypes.c_int
+        L.ssa_debug_enclosures.argtypes = [_vp, _vp, _sz, _vp, _sz, _vp, _vp,
+                                           ctypes.POINTER(ctypes.c_int)]
+        L.ssa_twiddle_table.restype = ctypes.c_int
+        L.ssa_twiddle_table.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int)]
+        L.ssa_probe_directed.restype = ctypes.c_int
+        L.ssa_probe_directed.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != SSA_OK:
+        raise SsaError("%s failed: %s" % (what, STATUS_NAMES.get(rc, rc)))
+
+
+def _dev_u8(x, device):
+    if isinstance(x, torch.Tensor):
+        t = x
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.uint8)))
+    t = t.to(device=device, dtype=torch.uint8).contiguous()
+    if t.device.type != "cuda":
+        raise SsaError("operands must live on the GPU")
+    return t
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def fft_size(na, nb, digit_bits=8):
+    return int(lib().ssa_fft_size(na, nb, digit_bits))
+
+
+class Plan:
+    """A plan for products with at most max_na x max_nb bytes."""
+
+    def __init__(self, max_na, max_nb, digit_bits=8, certify_mode=SSA_CERTIFY_ONE_INTEGER,
+                 stream=None, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.digit_bits = digit_bits
+        opts = PlanOpts(SSA_FP64, digit_bits, certify_mode, 0)
+        h = _vp()
+        with torch.cuda.device(self.device):
+            _check(lib().ssa_plan_create(ctypes.byref(h), max_na, max_nb, ctypes.byref(opts),
+                                         _vp(self.stream.cuda_stream)), "ssa_plan_create")
+        self.handle = h
+        self.max_na, self.max_nb = max_na, max_nb
+
+    def close(self):
+        if self.handle:
+            lib().ssa_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mul(self, a, b, out=None):
+        """Product of two byte vectors (tensors or arrays).  Returns (status, out)
+        with out a uint8 device tensor of len(a) + len(b) bytes."""
+        a = _dev_u8(a, self.device)
+        b = _dev_u8(b, self.device)
+        if out is None:
+            out = torch.empty(a.numel() + b.numel(), dtype=torch.uint8, device=self.device)
+        st = ctypes.c_int(-1)
+        _check(lib().ssa_mul(self.handle, a.data_ptr(), a.numel(), b.data_ptr(), b.numel(),
+                             out.data_ptr(), ctypes.byref(st)), "ssa_mul")
+        return st.value, out
+
+    def stats(self):
+        s = Stats()
+        _check(lib().ssa_get_stats(self.handle, ctypes.byref(s)), "ssa_get_stats")
+        return s.as_dict()
+
+    def debug_enclosures(self, a, b):
+        """(status, out, enclosures N x 4 float64 {re_lo, re_hi, im_lo, im_hi})."""
+        a = _dev_u8(a, self.device)
+        b = _dev_u8(b, self.device)
+        N = fft_size(a.numel(), b.numel(), self.digit_bits)
+        enc = torch.empty((N, 4), dtype=torch.float64, device=self.device)
+        out = torch.empty(a.numel() + b.numel(), dtype=torch.uint8, device=self.device)
+        st = ctypes.c_int(-1)
+        _check(lib().ssa_debug_enclosures(self.handle, a.data_ptr(), a.numel(), b.data_ptr(),
+                                          b.numel(), out.data_ptr(), enc.data_ptr(),
+                                          ctypes.byref(st)), "ssa_debug_enclosures")
+        return st.value, out, enc
+
+    def twiddles(self):
+        """(table Ntab x 2 float64 device tensor, error bound e, log2 Ntab)."""
+        n = fft_size(self.max_na, self.max_nb, self.digit_bits)
+        tab = torch.empty((n, 2), dtype=torch.float64, device=self.device)
+        e = ctypes.c_double(0)
+        lg = ctypes.c_int(0)
+        _check(lib().ssa_twiddle_table(self.handle, tab.data_ptr(), ctypes.byref(e),
+                                       ctypes.byref(lg)), "ssa_twiddle_table")
+        return tab[: 1 << lg.value], e.value, lg.value
+
+
+class Batch:
+    """Many products in one captured launch.  A, B: lists of uint8 device
+    tensors; outputs are allocated here (len(a) + len(b) bytes each)."""
+
+    def __init__(self, plan, A, B):
+        self.plan = plan
+        self.A = [_dev_u8(a, plan.device) for a in A]
+        self.B = [_dev_u8(b, plan.device) for b in B]
+        n = len(self.A)
+        if n != len(self.B) or n == 0:
+            raise SsaError("A and B must be non-empty and of equal length")
+        self.OUT = [torch.empty(a.numel() + b.numel(), dtype=torch.uint8, device=plan.device)
+                    for a, b in zip(self.A, self.B)]
+        self.status = torch.full((n,), -1, dtype=torch.int32, device=plan.device)
+        pa = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.A])
+        pb = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.B])
+        po = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.OUT])
+        na = (ctypes.c_size_t * n)(*[t.numel() for t in self.A])
+        nb = (ctypes.c_size_t * n)(*[t.numel() for t in self.B])
+        h = _vp()
+        _check(lib().ssa_batch_create(plan.handle, n, ctypes.cast(pa, _vp), ctypes.cast(na, _vp),
+                                      ctypes.cast(pb, _vp), ctypes.cast(nb, _vp),
+                                      ctypes.cast(po, _vp), ctypes.byref(h)), "ssa_batch_create")
+        self.handle = h
+        self.count = n
+
+    def run(self):
+        _check(lib().ssa_batch_run(self.handle, self.status.data_ptr()), "ssa_batch_run")
+        return self.status
+
+    def stats(self):
+        arr = (Stats * self.count)()
+        _check(lib().ssa_batch_stats(self.handle, ctypes.cast(arr, _vp)), "ssa_batch_stats")
+        return [s.as_dict() for s in arr]
+
+    def close(self):
+        if self.handle:
+            lib().ssa_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def probe_directed(op, a, b, c, stream=None):
+    """Device directed-rounding primitives (see include/ssa.h) on float64 tensors."""
+    a, b, c = (torch.as_tensor(x, dtype=torch.float64).cuda().contiguous() for x in (a, b, c))
+    out = torch.empty_like(a)
+    _check(lib().ssa_probe_directed(op, a.data_ptr(), b.data_ptr(), c.data_ptr(), out.data_ptr(),
+                                    a.numel(), _vp(_stream_handle(stream))), "ssa_probe_directed")
+    return out
+
+
+def mul(a, b, digit_bits=8, certify_mode=SSA_CERTIFY_ONE_INTEGER):
+    """One-off product of two byte arrays; returns (status, numpy uint8 product)."""
+    a = np.asarray(a, dtype=np.uint8)
+    b = np.asarray(b, dtype=np.uint8)
+    p = Plan(len(a), len(b), digit_bits=digit_bits, certify_mode=certify_mode)
+    try:
+        st, out = p.mul(a, b)
+        return st, out.cpu().numpy()
+    finally:
+        p.close()

@@ -1,0 +1,491 @@
+// C ABI (include/ssa.h): plans, single products, batches, diagnostics.
+//
+// A plan owns the certified twiddle table for its largest transform, the
+// scratch of one product and pinned staging for its descriptor and
+// statistics; ssa_mul only enqueues kernels and one small copy each way.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/ssa.h"
+#include "internal.hpp"
+#include "twiddle.hpp"
+
+using namespace ssa;
+
+namespace {
+
+constexpr int MAX_LOG_N = 23;  // column pass: N1 <= 2^11 (1024 threads)
+
+int ceil_log2(uint64_t v) {
+  int k = 0;
+  while ((uint64_t(1) << k) < v) ++k;
+  return k;
+}
+
+// Transform length exponent for L coefficients (zero padding up to 2^8).
+int log_n_for(uint64_t L) { return std::max(ceil_log2(L), SMALL_MIN_LOG); }
+
+uint64_t digits(size_t n, int bits) { return bits == 4 ? 2 * uint64_t(n) : uint64_t(n); }
+
+// Default launch shape of the three-pass path for N = 2^log_n.
+launch_cfg default_cfg(int log_n) {
+  launch_cfg c;
+  c.log_n1 = log_n / 2;
+  c.log_n2 = log_n - c.log_n1;
+  const int N1 = 1 << c.log_n1, N2 = 1 << c.log_n2;
+  c.cols = std::max(2, std::min(16, 2048 / N1));
+  c.rows = std::max(1, std::min(8, 1024 / N2));
+  return c;
+}
+
+bool hip_ok(hipError_t e) { return e == hipSuccess; }
+
+int status_from(const dev_stats &s) {
+  if (s.internal) return SSA_INTERNAL_ERROR;
+  if (s.too_wide) return SSA_ENCLOSURE_TOO_WIDE;
+  if (s.carry_err) return SSA_DEVICE_ERROR;
+  return SSA_OK;
+}
+
+ssa_stats to_public(const dev_stats &s, int log_n) {
+  ssa_stats o;
+  std::memset(&o, 0, sizeof(o));
+  uint64_t rb = s.max_rad_bits;
+  std::memcpy(&o.max_radius, &rb, sizeof(double));
+  o.half_int = s.half_int;
+  o.too_wide = s.too_wide;
+  o.internal = s.internal;
+  o.carry_err = s.carry_err;
+  o.log_n = static_cast<uint32_t>(log_n);
+  o.status = status_from(s);
+  return o;
+}
+
+bool kernels_configured = false;
+
+}  // namespace
+
+namespace ssa {
+hipError_t set_kernel_attributes();
+}
+
+struct ssa_plan {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  ssa_plan_opts opts{};
+  size_t max_na = 0, max_nb = 0;
+  int log_nmax = 0;
+  // twiddles
+  double2 *tab = nullptr;
+  int log_ntab = 0;
+  double e = 0.0;
+  unsigned long long *ebits = nullptr;
+  void *roots = nullptr;
+  // single-product scratch
+  ci *ya = nullptr, *yb = nullptr;
+  unsigned long long *c = nullptr;
+  dev_stats *st = nullptr;
+  uint32_t *tiles = nullptr;
+  task *d_task = nullptr;
+  task *h_task = nullptr;       // pinned
+  dev_stats *h_stats = nullptr; // pinned
+  ssa_stats last{};
+};
+
+struct ssa_batch {
+  ssa_plan *plan = nullptr;
+  size_t count = 0;
+  std::vector<int> order;  // task slot -> caller index
+  task *d_tasks = nullptr;
+  std::vector<task> h_tasks;
+  ci *arena = nullptr;
+  unsigned long long *carena = nullptr;
+  dev_stats *stats = nullptr;
+  uint32_t *tiles = nullptr;
+  int *d_status_slot = nullptr;  // by slot
+  int *d_status = nullptr;       // by caller index
+  int *d_order = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void free_plan(ssa_plan *p) {
+  if (!p) return;
+  hipFree(p->tab);
+  hipFree(p->ebits);
+  hipFree(p->roots);
+  hipFree(p->ya);
+  hipFree(p->yb);
+  hipFree(p->c);
+  hipFree(p->st);
+  hipFree(p->tiles);
+  hipFree(p->d_task);
+  if (p->h_task) hipHostFree(p->h_task);
+  if (p->h_stats) hipHostFree(p->h_stats);
+  delete p;
+}
+
+twtab_host tw_of(const ssa_plan *p) { return twtab_host{p->tab, p->log_ntab, p->e}; }
+
+// Enqueue one product class: all tasks [d_tasks, d_tasks + n) share log_n.
+hipError_t enqueue_class(const ssa_plan *p, const task *d_tasks, int n, int log_n, double *dbg,
+                         hipStream_t s) {
+  const int bits = p->opts.digit_bits, mode = p->opts.certify_mode;
+  if (log_n <= SMALL_MAX_LOG) return launch_small(d_tasks, n, log_n, bits, mode, tw_of(p), dbg, s);
+  return launch_multipass(d_tasks, n, log_n, default_cfg(log_n), bits, mode, tw_of(p), dbg, s);
+}
+
+ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
+                      uint8_t *out, double *dbg, ssa_status *status) {
+  if (!p || !a || !b || !out || !status || na == 0 || nb == 0 || na > p->max_na ||
+      nb > p->max_nb)
+    return SSA_INVALID_ARGUMENT;
+  const int bits = p->opts.digit_bits;
+  const uint64_t nda = digits(na, bits), ndb = digits(nb, bits);
+  const uint64_t L = nda + ndb - 1;
+  const int log_n = log_n_for(L);
+  task &t = *p->h_task;
+  std::memset(&t, 0, sizeof(t));
+  t.a = a;
+  t.b = b;
+  t.out = out;
+  t.na = static_cast<uint32_t>(na);
+  t.nb = static_cast<uint32_t>(nb);
+  t.nda = static_cast<uint32_t>(nda);
+  t.ndb = static_cast<uint32_t>(ndb);
+  t.L = static_cast<uint32_t>(L);
+  t.log_n = static_cast<uint32_t>(log_n);
+  t.ya = p->ya;
+  t.yb = p->yb;
+  t.c = p->c;
+  t.st = p->st;
+  t.tiles = p->tiles;
+  t.ntiles = static_cast<uint32_t>((na + nb + CARRY_TILE - 1) / CARRY_TILE);
+  hipStream_t s = p->stream;
+  if (!hip_ok(hipMemcpyAsync(p->d_task, p->h_task, sizeof(task), hipMemcpyHostToDevice, s)))
+    return SSA_DEVICE_ERROR;
+  if (!hip_ok(enqueue_class(p, p->d_task, 1, log_n, dbg, s))) return SSA_DEVICE_ERROR;
+  if (log_n > SMALL_MAX_LOG && !hip_ok(launch_carry(p->d_task, 1, t.ntiles, bits, s)))
+    return SSA_DEVICE_ERROR;
+  if (!hip_ok(hipMemcpyAsync(p->h_stats, p->st, sizeof(dev_stats), hipMemcpyDeviceToHost, s)))
+    return SSA_DEVICE_ERROR;
+  if (!hip_ok(hipStreamSynchronize(s))) return SSA_DEVICE_ERROR;
+  p->last = to_public(*p->h_stats, log_n);
+  *status = static_cast<ssa_status>(p->last.status);
+  return SSA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ssa_fft_size(size_t na, size_t nb, int digit_bits) {
+  if (na == 0 || nb == 0 || (digit_bits != 8 && digit_bits != 4)) return 0;
+  return size_t(1) << log_n_for(digits(na, digit_bits) + digits(nb, digit_bits) - 1);
+}
+
+ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
+                           const ssa_plan_opts *opts, void *stream) {
+  if (!plan) return SSA_INVALID_ARGUMENT;
+  *plan = nullptr;
+  ssa_plan_opts o{SSA_FP64, 8, SSA_CERTIFY_ONE_INTEGER, 0};
+  if (opts) o = *opts;
+  if (max_na == 0 || max_nb == 0 || (o.digit_bits != 8 && o.digit_bits != 4) ||
+      (o.certify_mode != SSA_CERTIFY_ONE_INTEGER && o.certify_mode != SSA_CERTIFY_HALF_INTEGER) ||
+      o.precision != SSA_FP64)
+    return SSA_INVALID_ARGUMENT;
+  const uint64_t L = digits(max_na, o.digit_bits) + digits(max_nb, o.digit_bits) - 1;
+  const int log_nmax = log_n_for(L);
+  if (log_nmax > MAX_LOG_N) return SSA_INVALID_ARGUMENT;
+  if (!kernels_configured) {
+    if (!hip_ok(set_kernel_attributes())) return SSA_DEVICE_ERROR;
+    kernels_configured = true;
+  }
+  ssa_plan *p = new (std::nothrow) ssa_plan();
+  if (!p) return SSA_OUT_OF_MEMORY;
+  p->stream = static_cast<hipStream_t>(stream);
+  hipGetDevice(&p->device);
+  p->opts = o;
+  p->max_na = max_na;
+  p->max_nb = max_nb;
+  p->log_nmax = log_nmax;
+  p->log_ntab = log_nmax;
+  const size_t N = size_t(1) << log_nmax;
+  const size_t ntiles = (max_na + max_nb + CARRY_TILE - 1) / CARRY_TILE;
+  bool ok = hip_ok(hipMalloc(&p->tab, sizeof(double2) << p->log_ntab)) &&
+            hip_ok(hipMalloc(&p->ebits, sizeof(unsigned long long))) &&
+            hip_ok(hipMalloc(&p->roots, twiddle_roots_bytes())) &&
+            hip_ok(hipMalloc(&p->c, sizeof(unsigned long long) * N)) &&
+            hip_ok(hipMalloc(&p->st, sizeof(dev_stats))) &&
+            hip_ok(hipMalloc(&p->tiles, sizeof(uint32_t) * ntiles)) &&
+            hip_ok(hipMalloc(&p->d_task, sizeof(task))) &&
+            hip_ok(hipHostMalloc(&p->h_task, sizeof(task), hipHostMallocDefault)) &&
+            hip_ok(hipHostMalloc(&p->h_stats, sizeof(dev_stats), hipHostMallocDefault));
+  if (ok && log_nmax > SMALL_MAX_LOG)
+    ok = hip_ok(hipMalloc(&p->ya, sizeof(ci) * N)) && hip_ok(hipMalloc(&p->yb, sizeof(ci) * N));
+  if (!ok) {
+    free_plan(p);
+    hipGetLastError();
+    return SSA_OUT_OF_MEMORY;
+  }
+  // certified twiddles: the bound e is read back once and passed by value
+  unsigned long long eb = 0;
+  ok = hip_ok(hipMemcpyAsync(p->ebits, &eb, sizeof(eb), hipMemcpyHostToDevice, p->stream)) &&
+       hip_ok(make_twiddles(p->log_ntab, p->tab, p->ebits, p->roots, p->stream)) &&
+       hip_ok(hipMemcpyAsync(&eb, p->ebits, sizeof(eb), hipMemcpyDeviceToHost, p->stream)) &&
+       hip_ok(hipStreamSynchronize(p->stream));
+  if (!ok) {
+    free_plan(p);
+    return SSA_DEVICE_ERROR;
+  }
+  std::memcpy(&p->e, &eb, sizeof(double));
+  *plan = p;
+  return SSA_OK;
+}
+
+void ssa_plan_destroy(ssa_plan *plan) {
+  if (!plan) return;
+  hipStreamSynchronize(plan->stream);
+  free_plan(plan);
+}
+
+ssa_status ssa_mul(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
+                   uint8_t *out, ssa_status *status) {
+  return run_single(plan, a, na, b, nb, out, nullptr, status);
+}
+
+ssa_status ssa_debug_enclosures(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b,
+                                size_t nb, uint8_t *out, double *enc_dev, ssa_status *status) {
+  if (!enc_dev) return SSA_INVALID_ARGUMENT;
+  return run_single(plan, a, na, b, nb, out, enc_dev, status);
+}
+
+ssa_status ssa_get_stats(const ssa_plan *plan, ssa_stats *stats_host) {
+  if (!plan || !stats_host) return SSA_INVALID_ARGUMENT;
+  *stats_host = plan->last;
+  return SSA_OK;
+}
+
+ssa_status ssa_twiddle_table(const ssa_plan *plan, double *tab_dev, double *e_host,
+                             int *log_ntab_host) {
+  if (!plan || !tab_dev || !e_host || !log_ntab_host) return SSA_INVALID_ARGUMENT;
+  if (!hip_ok(hipMemcpyAsync(tab_dev, plan->tab, sizeof(double2) << plan->log_ntab,
+                             hipMemcpyDeviceToDevice, plan->stream)) ||
+      !hip_ok(hipStreamSynchronize(plan->stream)))
+    return SSA_DEVICE_ERROR;
+  *e_host = plan->e;
+  *log_ntab_host = plan->log_ntab;
+  return SSA_OK;
+}
+
+ssa_status ssa_probe_directed(int op, const double *a, const double *b, const double *c,
+                              double *out, size_t n, void *stream) {
+  if (!a || !b || !c || !out || op < 0 || op > 5) return SSA_INVALID_ARGUMENT;
+  if (n == 0) return SSA_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!hip_ok(launch_directed_probe(op, a, b, c, out, n, s)) || !hip_ok(hipStreamSynchronize(s)))
+    return SSA_DEVICE_ERROR;
+  return SSA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+
+void ssa_batch_destroy(ssa_batch *bt) {
+  if (!bt) return;
+  if (bt->plan) hipStreamSynchronize(bt->plan->stream);
+  if (bt->exec) hipGraphExecDestroy(bt->exec);
+  if (bt->graph) hipGraphDestroy(bt->graph);
+  hipFree(bt->d_tasks);
+  hipFree(bt->arena);
+  hipFree(bt->carena);
+  hipFree(bt->stats);
+  hipFree(bt->tiles);
+  hipFree(bt->d_status_slot);
+  hipFree(bt->d_status);
+  hipFree(bt->d_order);
+  delete bt;
+}
+
+}  // extern "C"
+
+namespace ssa {
+// Scatter statuses from task order back to caller order.
+hipError_t launch_scatter_status(const int *slot_status, const int *order, int n, int *out,
+                                 hipStream_t s);
+}
+
+extern "C" {
+
+ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *a,
+                            const size_t *na, const uint8_t *const *b, const size_t *nb,
+                            uint8_t *const *out, ssa_batch **batch) {
+  if (!batch) return SSA_INVALID_ARGUMENT;
+  *batch = nullptr;
+  if (!plan || count == 0 || !a || !na || !b || !nb || !out || count > (1u << 24))
+    return SSA_INVALID_ARGUMENT;
+  const int bits = plan->opts.digit_bits;
+  std::vector<int> lg(count);
+  for (size_t i = 0; i < count; ++i) {
+    if (!a[i] || !b[i] || !out[i] || na[i] == 0 || nb[i] == 0 || na[i] > plan->max_na ||
+        nb[i] > plan->max_nb)
+      return SSA_INVALID_ARGUMENT;
+    lg[i] = log_n_for(digits(na[i], bits) + digits(nb[i], bits) - 1);
+  }
+  ssa_batch *bt = new (std::nothrow) ssa_batch();
+  if (!bt) return SSA_OUT_OF_MEMORY;
+  bt->plan = plan;
+  bt->count = count;
+  // group by transform length, largest first
+  bt->order.resize(count);
+  for (size_t i = 0; i < count; ++i) bt->order[i] = static_cast<int>(i);
+  std::stable_sort(bt->order.begin(), bt->order.end(),
+                   [&](int x, int y) { return lg[x] > lg[y]; });
+  // scratch sizes
+  size_t arena_elems = 0, c_elems = 0, tiles = 0;
+  for (size_t i = 0; i < count; ++i) {
+    const size_t N = size_t(1) << lg[i];
+    if (lg[i] > SMALL_MAX_LOG) {
+      arena_elems += 2 * N;
+      c_elems += N;
+      tiles += (na[i] + nb[i] + CARRY_TILE - 1) / CARRY_TILE;
+    }
+  }
+  bool ok = hip_ok(hipMalloc(&bt->d_tasks, sizeof(task) * count)) &&
+            hip_ok(hipMalloc(&bt->stats, sizeof(dev_stats) * count)) &&
+            hip_ok(hipMalloc(&bt->d_status_slot, sizeof(int) * count)) &&
+            hip_ok(hipMalloc(&bt->d_status, sizeof(int) * count)) &&
+            hip_ok(hipMalloc(&bt->d_order, sizeof(int) * count));
+  if (ok && arena_elems)
+    ok = hip_ok(hipMalloc(&bt->arena, sizeof(ci) * arena_elems)) &&
+         hip_ok(hipMalloc(&bt->carena, sizeof(unsigned long long) * c_elems)) &&
+         hip_ok(hipMalloc(&bt->tiles, sizeof(uint32_t) * std::max<size_t>(tiles, 1)));
+  if (!ok) {
+    ssa_batch_destroy(bt);
+    hipGetLastError();
+    return SSA_OUT_OF_MEMORY;
+  }
+  bt->h_tasks.resize(count);
+  size_t ao = 0, co = 0, to = 0;
+  for (size_t s = 0; s < count; ++s) {
+    const int i = bt->order[s];
+    task &t = bt->h_tasks[s];
+    std::memset(&t, 0, sizeof(t));
+    t.a = a[i];
+    t.b = b[i];
+    t.out = out[i];
+    t.na = static_cast<uint32_t>(na[i]);
+    t.nb = static_cast<uint32_t>(nb[i]);
+    t.nda = static_cast<uint32_t>(digits(na[i], bits));
+    t.ndb = static_cast<uint32_t>(digits(nb[i], bits));
+    t.L = t.nda + t.ndb - 1;
+    t.log_n = static_cast<uint32_t>(lg[i]);
+    t.st = bt->stats + s;
+    if (lg[i] > SMALL_MAX_LOG) {
+      const size_t N = size_t(1) << lg[i];
+      t.ya = bt->arena + ao;
+      t.yb = bt->arena + ao + N;
+      ao += 2 * N;
+      t.c = bt->carena + co;
+      co += N;
+      t.ntiles = static_cast<uint32_t>((na[i] + nb[i] + CARRY_TILE - 1) / CARRY_TILE);
+      t.tiles = bt->tiles + to;
+      to += t.ntiles;
+    }
+  }
+  hipStream_t st = plan->stream;
+  ok = hip_ok(hipMemcpyAsync(bt->d_tasks, bt->h_tasks.data(), sizeof(task) * count,
+                             hipMemcpyHostToDevice, st)) &&
+       hip_ok(hipMemcpyAsync(bt->d_order, bt->order.data(), sizeof(int) * count,
+                             hipMemcpyHostToDevice, st)) &&
+       hip_ok(hipStreamSynchronize(st));
+  if (!ok) {
+    ssa_batch_destroy(bt);
+    return SSA_DEVICE_ERROR;
+  }
+  // Capture: per length class one launch (or three), then one carry scan over
+  // every multi-pass product, then the status scatter.
+  hipStream_t cs = nullptr;
+  ok = hip_ok(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  if (ok) ok = hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  size_t s0 = 0;
+  uint32_t max_tiles = 0;
+  size_t n_multi = 0;
+  while (ok && s0 < count) {
+    size_t s1 = s0;
+    const int l = static_cast<int>(bt->h_tasks[s0].log_n);
+    while (s1 < count && static_cast<int>(bt->h_tasks[s1].log_n) == l) {
+      max_tiles = std::max(max_tiles, bt->h_tasks[s1].ntiles);
+      ++s1;
+    }
+    if (l > SMALL_MAX_LOG) n_multi = s1;  // multi-pass classes come first
+    ok = hip_ok(enqueue_class(plan, bt->d_tasks + s0, static_cast<int>(s1 - s0), l, nullptr, cs));
+    s0 = s1;
+  }
+  if (ok && n_multi) ok = hip_ok(launch_carry(bt->d_tasks, static_cast<int>(n_multi), max_tiles, bits, cs));
+  if (ok) ok = hip_ok(launch_status(bt->d_tasks, static_cast<int>(count), bt->d_status_slot, cs));
+  if (ok) ok = hip_ok(launch_scatter_status(bt->d_status_slot, bt->d_order, static_cast<int>(count), bt->d_status, cs));
+  hipGraph_t g = nullptr;
+  if (cs) {
+    const hipError_t ec = hipStreamEndCapture(cs, &g);
+    ok = ok && hip_ok(ec);
+  }
+  if (ok) {
+    bt->graph = g;
+    ok = hip_ok(hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0));
+  } else if (g) {
+    hipGraphDestroy(g);
+  }
+  if (cs) hipStreamDestroy(cs);
+  if (!ok) {
+    ssa_batch_destroy(bt);
+    hipGetLastError();
+    return SSA_DEVICE_ERROR;
+  }
+  *batch = bt;
+  return SSA_OK;
+}
+
+ssa_status ssa_batch_run(ssa_batch *bt, int *status_dev) {
+  if (!bt || !status_dev) return SSA_INVALID_ARGUMENT;
+  hipStream_t s = bt->plan->stream;
+  if (!hip_ok(hipGraphLaunch(bt->exec, s))) return SSA_DEVICE_ERROR;
+  if (!hip_ok(hipMemcpyAsync(status_dev, bt->d_status, sizeof(int) * bt->count,
+                             hipMemcpyDeviceToDevice, s)))
+    return SSA_DEVICE_ERROR;
+  return SSA_OK;
+}
+
+ssa_status ssa_batch_stats(ssa_batch *bt, ssa_stats *stats_host) {
+  if (!bt || !stats_host) return SSA_INVALID_ARGUMENT;
+  std::vector<dev_stats> h(bt->count);
+  hipStream_t s = bt->plan->stream;
+  if (!hip_ok(hipMemcpyAsync(h.data(), bt->stats, sizeof(dev_stats) * bt->count,
+                             hipMemcpyDeviceToHost, s)) ||
+      !hip_ok(hipStreamSynchronize(s)))
+    return SSA_DEVICE_ERROR;
+  for (size_t k = 0; k < bt->count; ++k)
+    stats_host[bt->order[k]] = to_public(h[k], static_cast<int>(bt->h_tasks[k].log_n));
+  return SSA_OK;
+}
+
+ssa_status ssa_mul_batch(ssa_plan *plan, size_t count, const uint8_t *const *a, const size_t *na,
+                         const uint8_t *const *b, const size_t *nb, uint8_t *const *out,
+                         int *status_dev) {
+  ssa_batch *bt = nullptr;
+  ssa_status r = ssa_batch_create(plan, count, a, na, b, nb, out, &bt);
+  if (r != SSA_OK) return r;
+  r = ssa_batch_run(bt, status_dev);
+  if (r == SSA_OK && !hip_ok(hipStreamSynchronize(plan->stream))) r = SSA_DEVICE_ERROR;
+  ssa_batch_destroy(bt);
+  return r;
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// Shared declarations between the kernels and the C-ABI implementation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ia.hpp"
+
+namespace ssa {
+
+// Per-product statistics, accumulated on the device.
+struct dev_stats {
+  unsigned long long max_rad_bits;  // bit pattern of max real-part radius (>= 0)
+  unsigned long long half_int;      // enclosures containing a half-integer
+  unsigned int too_wide;            // enclosures holding more than one integer
+  unsigned int internal;            // enclosures that cannot be rigorous
+  unsigned int carry_err;           // carry scan gave up waiting (never expected)
+  unsigned int ticket;              // carry-scan tile ticket counter
+};
+
+// One product as the kernels see it.  Sizes are in digits of the chosen base.
+struct task {
+  const uint8_t *a;
+  const uint8_t *b;
+  uint8_t *out;
+  uint32_t na, nb;        // operand bytes
+  uint32_t nda, ndb;      // operand digits (bytes, or nibbles when digit_bits == 4)
+  uint32_t L;             // coefficient count nda + ndb - 1
+  uint32_t log_n;         // transform length N = 2^log_n
+  ci *ya;                 // multi-pass scratch: N elements per operand
+  ci *yb;
+  unsigned long long *c;  // coefficients (N entries)
+  dev_stats *st;
+  uint32_t *tiles;        // carry-scan tile status words
+  uint32_t ntiles;
+  uint32_t pad;
+};
+
+enum { CERT_ONE_INTEGER = 0, CERT_HALF_INTEGER = 1 };
+
+// Tile of the carry scan: threads x positions per thread.
+static constexpr int CARRY_THREADS = 256;
+static constexpr int CARRY_PER_THREAD = 16;
+static constexpr int CARRY_TILE = CARRY_THREADS * CARRY_PER_THREAD;
+
+// Largest transform done by one workgroup holding everything in LDS.
+static constexpr int SMALL_MAX_LOG = 12;
+static constexpr int SMALL_MIN_LOG = 8;
+
+struct launch_cfg {
+  int log_n1;  // column transform length (multi-pass)
+  int log_n2;  // row transform length
+  int cols;    // columns per workgroup in the column passes
+  int rows;    // rows per workgroup in the row pass
+};
+
+struct twtab_host {
+  const double2 *tab;
+  int log_ntab;
+  double e;
+};
+
+// dbg (nullable): N x 4 doubles {re_lo, re_hi, im_lo, im_hi} of the final
+// enclosures of task 0, written before certification.
+hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bits, int cert_mode,
+                        const twtab_host &tw, double *dbg, hipStream_t s);
+hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const launch_cfg &cfg,
+                            int digit_bits, int cert_mode, const twtab_host &tw, double *dbg,
+                            hipStream_t s);
+hipError_t launch_carry(const task *d_tasks, int ntasks, uint32_t max_tiles, int digit_bits,
+                        hipStream_t s);
+hipError_t launch_status(const task *d_tasks, int ntasks, int *d_status, hipStream_t s);
+hipError_t launch_directed_probe(int op, const double *a, const double *b, const double *c,
+                                 double *out, size_t n, hipStream_t s);
+
+}  // namespace ssa

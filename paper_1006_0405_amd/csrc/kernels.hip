@@ -1,0 +1,603 @@
+// Kernels of the rigorous interval Schoenhage-Strassen product on gfx950.
+//
+// Fast convolution (paper section 2.3) over rectangular complex intervals
+// (section 2.5), certification (section 1: the unique integer in each
+// enclosure, else an error) and carries (section 2.4).
+//
+// Two shapes of the same computation:
+//  * N <= 2^12: one workgroup per product, everything in LDS (k_small).
+//  * larger N = N1 * N2: three passes of the four-step factorisation
+//      X[k1 + N1 k2] = sum_n2 omega_N2^{n2 k2} omega_N^{n2 k1} sum_n1 x[N2 n1 + n2] omega_N1^{n1 k1}
+//    k_col_fwd : length-N1 column DFTs of both operands, twiddle omega_N^{n2 k1},
+//                rows k1 stored contiguously;
+//    k_row     : per row k1 the length-N2 DFTs of both operands, the pointwise
+//                product, and the first half of the inverse (length-N2 DFT of the
+//                conjugate, conjugate twiddle) -- the spectrum never leaves the chip;
+//    k_col_inv : length-N1 inverse column DFTs, the 1/N scale, certification;
+//    k_carry   : carries as a generate/propagate scan with decoupled look-back.
+// The inverse DFT is computed as conj(DFT(conj(.)))/N, so a single forward
+// interval DFT serves every transform; conjugation is exact.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft.hpp"
+#include "internal.hpp"
+
+namespace ssa {
+
+// ---------------------------------------------------------------------------
+// Digits (section 2: little-endian base-b vectors); base 16 splits each byte
+// into (low nibble, high nibble).
+
+__device__ __forceinline__ uint32_t digit(const uint8_t *p, uint32_t nd, uint32_t i, int bits) {
+  if (i >= nd) return 0u;
+  if (bits == 8) return p[i];
+  const uint32_t byte = p[i >> 1];
+  return (i & 1u) ? (byte >> 4) : (byte & 15u);
+}
+
+// ---------------------------------------------------------------------------
+// Certification of one enclosure.
+
+struct cert_acc {
+  double rad;
+  uint32_t too_wide, internal, half;
+};
+
+static constexpr double TWO52 = 4503599627370496.0;
+
+// For i < L the real part [lo, hi] must hold exactly one integer:
+// ceil(lo) == floor(hi) (with lo = -rn, ceil(lo) = -floor(rn)).  Several
+// integers: too wide.  No integer, a negative one, or an imaginary part that
+// excludes 0: impossible for a rigorous enclosure, counted as internal.  The
+// padded tail i >= L must contain 0 in both parts.
+__device__ __forceinline__ unsigned long long certify(const ci &z, uint32_t i, uint32_t L,
+                                                      int mode, cert_acc &acc) {
+  if (i >= L) {
+    if (!(z.rn >= 0.0 && z.rh >= 0.0 && z.in >= 0.0 && z.ih >= 0.0)) acc.internal++;
+    return 0ull;
+  }
+  const double rad = ru_mul(ru_add(z.rn, z.rh), 0.5);
+  acc.rad = rad > acc.rad ? rad : acc.rad;
+  const double m = -dfloor(z.rn);  // ceil(lo)
+  const double M = dfloor(z.rh);   // floor(hi)
+  const bool im0 = z.in >= 0.0 && z.ih >= 0.0;
+  const double h_lo = -dfloor(ru_add(z.rn, 0.5));  // ceil(lo - 1/2)
+  const double h_hi = dfloor(ru_add(z.rh, -0.5));  // floor(hi - 1/2)
+  const bool half = h_lo <= h_hi;
+  if (half) acc.half++;
+  if (!(m <= M) || !im0) {
+    acc.internal++;
+    return 0ull;
+  }
+  if (m < M || (mode == CERT_HALF_INTEGER && half)) {
+    acc.too_wide++;
+    return 0ull;
+  }
+  if (!(m >= 0.0 && m < TWO52)) {
+    acc.internal++;
+    return 0ull;
+  }
+  // m is an integer in [0, 2^52): m + 2^52 is exact and its low mantissa bits are m.
+  const double t = ru_add(m, TWO52);
+  return static_cast<unsigned long long>(__double_as_longlong(t)) - 0x4330000000000000ull;
+}
+
+__device__ __forceinline__ void dbg_store(double *dbg, uint32_t i, const ci &z) {
+  double2 *p = reinterpret_cast<double2 *>(dbg + 4 * static_cast<size_t>(i));
+  p[0] = make_double2(-z.rn, z.rh);
+  p[1] = make_double2(-z.in, z.ih);
+}
+
+// Block-wide reduction of the certification counters into LDS words, then
+// (optionally) one atomic per block into the product's statistics.
+struct cert_shared {
+  unsigned long long rad_bits;
+  unsigned long long half;
+  unsigned int too_wide, internal;
+};
+
+__device__ __forceinline__ void cert_reduce(cert_shared &sh, const cert_acc &acc) {
+  // acc.rad >= 0: the bit pattern orders like the value
+  unsigned long long rb = static_cast<unsigned long long>(__double_as_longlong(acc.rad));
+  uint32_t tw = acc.too_wide, in = acc.internal, hf = acc.half;
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(rb, off);
+    rb = o > rb ? o : rb;
+    tw += __shfl_xor(tw, off);
+    in += __shfl_xor(in, off);
+    hf += __shfl_xor(hf, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&sh.rad_bits, rb);
+    if (hf) atomicAdd(&sh.half, static_cast<unsigned long long>(hf));
+    if (tw) atomicAdd(&sh.too_wide, tw);
+    if (in) atomicAdd(&sh.internal, in);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Carries.
+//
+// The product is z = sum_i c_i 256^i with c_i < 2^48 (base-16 coefficients are
+// first paired: C_j = c_{2j} + 16 c_{2j+1}).  Split every coefficient into
+// bytes: s_p = sum_{t<6} byte_t(C_{p-t}) <= 6 * 255, then
+// u_p = (s_p mod 256) + floor(s_{p-1} / 256) <= 260, so that z = sum u_p 256^p
+// and the carry into every position is 0 or 1.  Position p generates a carry
+// when u_p >= 256 and propagates one when u_p == 255; the carries are the
+// prefix of these (generate, propagate) pairs.  Within a wavefront the prefix
+// is an integer addition over the lane masks: with x = g | p, the carry into
+// lane l is bit l of (x + g + cin) ^ x ^ g.
+
+template <class F>
+__device__ __forceinline__ uint32_t s_at(F C, long long p) {
+  uint32_t s = 0;
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    const unsigned long long v = C(p - t);
+    s += static_cast<uint32_t>((v >> (8 * t)) & 255ull);
+  }
+  return s;
+}
+
+// Tile of CH positions per thread.  `tile_cin(G, P)` is called by thread 0
+// with the tile's aggregate (carry-out for carry-in 0, all-propagate) and
+// returns the tile's carry-in.
+template <int CH, class F, class TC>
+__device__ __forceinline__ void carry_block(F C, long long p0, uint32_t nout, uint8_t *out,
+                                            bool zero, TC tile_cin, uint32_t *sh_waves) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const long long q0 = p0 + static_cast<long long>(tid) * CH;
+  uint32_t u[CH];
+  uint32_t sprev = s_at(C, q0 - 1);
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    const uint32_t s = s_at(C, q0 + k);
+    u[k] = (s & 255u) + (sprev >> 8);
+    sprev = s;
+  }
+  // thread aggregate
+  uint32_t G = 0, P = 1;
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    const uint32_t g = u[k] >= 256u, pr = u[k] == 255u;
+    G = g | (pr & G);
+    P = P & pr;
+  }
+  const unsigned long long gm = __ballot(G != 0), pm = __ballot(P != 0);
+  const unsigned long long x = gm | pm;
+  const unsigned long long s0 = x + gm;
+  const uint32_t wG = s0 < x ? 1u : 0u;  // overflow: carry out of lane 63
+  const uint32_t wP = (pm == ~0ull) ? 1u : 0u;
+  if (lane == 0) sh_waves[wave] = (wG << 1) | wP;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t TG = 0, TP = 1;
+    for (int w = 0; w < nwaves; ++w) {
+      const uint32_t a = sh_waves[w];
+      TG = ((a >> 1) & 1u) | ((a & 1u) & TG);
+      TP &= a & 1u;
+    }
+    uint32_t cin = zero ? 0u : tile_cin(TG, TP);
+    for (int w = 0; w < nwaves; ++w) {
+      const uint32_t a = sh_waves[w];
+      sh_waves[w] = (sh_waves[w] & 3u) | (cin << 2);
+      cin = ((a >> 1) & 1u) | ((a & 1u) & cin);
+    }
+  }
+  __syncthreads();
+  const unsigned long long cw = (sh_waves[wave] >> 2) & 1u;
+  const unsigned long long carries = (x + gm + cw) ^ x ^ gm;
+  uint32_t cy = static_cast<uint32_t>((carries >> lane) & 1ull);
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    const uint32_t v = u[k] + cy;
+    cy = v >> 8;
+    const long long p = q0 + k;
+    if (p >= 0 && p < static_cast<long long>(nout)) out[p] = zero ? 0 : static_cast<uint8_t>(v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_small: the whole product in one workgroup of N/4 threads, N = 2^log_n,
+// 2^8 <= N <= 2^12.  LDS: N complex intervals (reused for the coefficients).
+
+__global__ __launch_bounds__(1024) void k_small(const task *tasks, int log_n, int bits, int mode,
+                                                twtab T, double *dbg) {
+  extern __shared__ ci lds[];
+  __shared__ cert_shared sh;
+  __shared__ uint32_t sh_waves[16];
+  const uint32_t z = enter_round_up();
+  const task tk = after_mode(tasks, z)[blockIdx.x];
+  T.tab = after_mode(T.tab, z);
+  const int Q = 1 << (log_n - 2);
+  const int j = threadIdx.x;
+  if (j == 0) sh = cert_shared{0ull, 0ull, 0u, 0u};
+
+  ci va[4], vb[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t i = j + r * Q;
+    va[r] = ci_thin_real(static_cast<double>(digit(tk.a, tk.nda, i, bits)));
+    vb[r] = ci_thin_real(static_cast<double>(digit(tk.b, tk.ndb, i, bits)));
+  }
+  fft_group(va, j, log_n, lds, 1, T);
+  fft_group(vb, j, log_n, lds, 1, T);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) va[r] = ci_conj(ci_mul(va[r], vb[r]));
+  fft_group(va, j, log_n, lds, 1, T);
+  const double scale = ldexp(1.0, -log_n);
+  cert_acc acc{0.0, 0u, 0u, 0u};
+  unsigned long long cv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t i = j + r * Q;
+    const ci v = ci_scale(ci_conj(va[r]), scale);
+    if (dbg != nullptr && blockIdx.x == 0) dbg_store(dbg, i, v);
+    cv[r] = certify(v, i, tk.L, mode, acc);
+  }
+  cert_reduce(sh, acc);
+  __syncthreads();  // LDS free again; counters final
+  unsigned long long *cl = reinterpret_cast<unsigned long long *>(lds);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) cl[j + r * Q] = cv[r];
+  __syncthreads();
+  const bool failed = (sh.too_wide + sh.internal) != 0u;
+  const uint32_t L = tk.L;
+  const uint32_t nout = tk.na + tk.nb;
+  if (bits == 8) {
+    auto C = [&](long long q) -> unsigned long long {
+      return (q >= 0 && q < static_cast<long long>(L)) ? cl[q] : 0ull;
+    };
+    carry_block<8>(C, 0, nout, tk.out, failed, [](uint32_t, uint32_t) { return 0u; }, sh_waves);
+  } else {
+    auto C = [&](long long q) -> unsigned long long {
+      if (q < 0) return 0ull;
+      const long long i0 = 2 * q, i1 = 2 * q + 1;
+      const unsigned long long lo = i0 < static_cast<long long>(L) ? cl[i0] : 0ull;
+      const unsigned long long hi = i1 < static_cast<long long>(L) ? cl[i1] : 0ull;
+      return lo + 16ull * hi;
+    };
+    carry_block<8>(C, 0, nout, tk.out, failed, [](uint32_t, uint32_t) { return 0u; }, sh_waves);
+  }
+  if (j == 0) {
+    dev_stats *st = tk.st;
+    st->max_rad_bits = sh.rad_bits;
+    st->half_int = sh.half;
+    st->too_wide = sh.too_wide;
+    st->internal = sh.internal;
+    st->carry_err = 0u;
+    st->ticket = 0u;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Multi-pass kernels.
+
+// Twiddle omega_N^t for t = (a * b) mod N, from the table of omega_Ntab.
+__device__ __forceinline__ uint32_t tw_index(uint32_t a, uint32_t b, int log_n, int log_ntab) {
+  const uint32_t t = (a * b) & ((1u << log_n) - 1u);
+  return t << (log_ntab - log_n);
+}
+
+// Columns: thread (c, j) with c = tid % C fastest, so that the C columns of a
+// workgroup are adjacent in memory.  grid = (N2 / C, 2 operands, tasks).
+__global__ __launch_bounds__(1024) void k_col_fwd(const task *tasks, int log_n1, int log_n2,
+                                                  int C, int bits, twtab T) {
+  extern __shared__ ci lds[];
+  const uint32_t z = enter_round_up();
+  const task tk = after_mode(tasks, z)[blockIdx.z];
+  T.tab = after_mode(T.tab, z);
+  const int log_n = log_n1 + log_n2;
+  const uint32_t N2 = 1u << log_n2;
+  const int Q = 1 << (log_n1 - 2);
+  const int c = threadIdx.x % C, j = threadIdx.x / C;
+  const uint32_t n2 = blockIdx.x * C + c;
+  const bool opb = blockIdx.y != 0;
+  if (blockIdx.x == 0 && !opb) {  // reset this product's statistics and scan state
+    if (threadIdx.x == 0) {
+      tk.st->max_rad_bits = 0ull;
+      tk.st->half_int = 0ull;
+      tk.st->too_wide = 0u;
+      tk.st->internal = 0u;
+      tk.st->carry_err = 0u;
+      tk.st->ticket = 0u;
+    }
+    for (uint32_t t = threadIdx.x; t < tk.ntiles; t += blockDim.x) tk.tiles[t] = 0u;
+  }
+  const uint8_t *p = opb ? tk.b : tk.a;
+  const uint32_t nd = opb ? tk.ndb : tk.nda;
+  ci v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t n1 = j + r * Q;
+    v[r] = ci_thin_real(static_cast<double>(digit(p, nd, (n1 << log_n2) + n2, bits)));
+  }
+  fft_group(v, j, log_n1, lds + c, C, T);
+  ci *Y = opb ? tk.yb : tk.ya;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t k1 = j + q * Q;
+    const ci w = apply_tw(v[q], T, tw_index(n2, k1, log_n, T.log_ntab));
+    gst(Y, (static_cast<size_t>(k1) << log_n2) + n2, w);
+  }
+}
+
+// Rows: R rows k1 per workgroup, N2/4 threads per row.  grid = (N1 / R, tasks).
+__global__ __launch_bounds__(1024) void k_row(const task *tasks, int log_n1, int log_n2, int R,
+                                              twtab T) {
+  extern __shared__ ci lds[];
+  const uint32_t z = enter_round_up();
+  const task tk = after_mode(tasks, z)[blockIdx.y];
+  T.tab = after_mode(T.tab, z);
+  const int log_n = log_n1 + log_n2;
+  const int Q = 1 << (log_n2 - 2);
+  const int g = threadIdx.x / Q, j = threadIdx.x % Q;
+  const uint32_t k1 = blockIdx.x * R + g;
+  ci *lg = lds + (static_cast<size_t>(g) << log_n2);
+  const size_t row = static_cast<size_t>(k1) << log_n2;
+  ci va[4], vb[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    va[r] = gld(tk.ya, row + j + r * Q);
+    vb[r] = gld(tk.yb, row + j + r * Q);
+  }
+  fft_group(va, j, log_n2, lg, 1, T);
+  fft_group(vb, j, log_n2, lg, 1, T);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) va[r] = ci_conj(ci_mul(va[r], vb[r]));
+  fft_group(va, j, log_n2, lg, 1, T);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t n2 = j + q * Q;
+    const ci w = ci_conj(apply_tw(va[q], T, tw_index(n2, k1, log_n, T.log_ntab)));
+    gst(tk.ya, row + n2, w);
+  }
+}
+
+// Inverse columns + scale + certification.  grid = (N2 / C, tasks).
+__global__ __launch_bounds__(1024) void k_col_inv(const task *tasks, int log_n1, int log_n2, int C,
+                                                  int mode, twtab T, double *dbg) {
+  extern __shared__ ci lds[];
+  __shared__ cert_shared sh;
+  const uint32_t z = enter_round_up();
+  const task tk = after_mode(tasks, z)[blockIdx.y];
+  T.tab = after_mode(T.tab, z);
+  const int log_n = log_n1 + log_n2;
+  const int Q = 1 << (log_n1 - 2);
+  const int c = threadIdx.x % C, j = threadIdx.x / C;
+  const uint32_t n2 = blockIdx.x * C + c;
+  if (threadIdx.x == 0) sh = cert_shared{0ull, 0ull, 0u, 0u};
+  ci v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t k1 = j + r * Q;
+    v[r] = ci_conj(gld(tk.ya, (static_cast<size_t>(k1) << log_n2) + n2));
+  }
+  fft_group(v, j, log_n1, lds + c, C, T);
+  const double scale = ldexp(1.0, -log_n);
+  cert_acc acc{0.0, 0u, 0u, 0u};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t n1 = j + q * Q;
+    const uint32_t i = (n1 << log_n2) + n2;
+    const ci w = ci_scale(ci_conj(v[q]), scale);
+    if (dbg != nullptr && blockIdx.y == 0) dbg_store(dbg, i, w);
+    tk.c[i] = certify(w, i, tk.L, mode, acc);
+  }
+  cert_reduce(sh, acc);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicMax(&tk.st->max_rad_bits, sh.rad_bits);
+    if (sh.half) atomicAdd(&tk.st->half_int, sh.half);
+    if (sh.too_wide) atomicAdd(&tk.st->too_wide, sh.too_wide);
+    if (sh.internal) atomicAdd(&tk.st->internal, sh.internal);
+  }
+}
+
+// Decoupled look-back (Merrill & Garland): tile status word = flag << 2 | bits,
+// flag 1: aggregate (G << 1 | P), flag 2: inclusive carry-out.  Tile numbers
+// come from a ticket counter in start order, so every tile looked at belongs to
+// a workgroup that is already running and never waits itself before
+// publishing its aggregate: the wait always ends.  A generous spin limit turns
+// an impossible hang into a reported error instead.
+static constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+__device__ uint32_t lookback(uint32_t *tiles, uint32_t tile, uint32_t G, uint32_t P,
+                             unsigned int *err) {
+  if (tile == 0) {
+    __hip_atomic_store(&tiles[0], (2u << 2) | G, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return 0u;
+  }
+  __hip_atomic_store(&tiles[tile], (1u << 2) | (G << 1) | P, __ATOMIC_RELEASE,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t cin = 0u;
+  int idx = static_cast<int>(tile) - 1;
+  uint32_t spins = 0u;
+  while (idx >= 0) {
+    const uint32_t w = __hip_atomic_load(&tiles[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t f = w >> 2;
+    if (f == 0u) {
+      if (++spins > SPIN_LIMIT) {
+        atomicAdd(err, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    if (f == 2u) {
+      cin = w & 1u;
+      break;
+    }
+    if ((w >> 1) & 1u) {
+      cin = 1u;
+      break;
+    }
+    if (!(w & 1u)) {
+      cin = 0u;
+      break;
+    }
+    --idx;  // predecessor propagates: look further back
+  }
+  __hip_atomic_store(&tiles[tile], (2u << 2) | (G | (P & cin)), __ATOMIC_RELEASE,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  return cin;
+}
+
+// grid = (max tiles, tasks), CARRY_THREADS threads.
+__global__ __launch_bounds__(CARRY_THREADS) void k_carry(const task *tasks, int bits) {
+  __shared__ uint32_t sh_waves[CARRY_THREADS / 64];
+  __shared__ uint32_t sh_tile;
+  const task tk = tasks[blockIdx.y];
+  if (blockIdx.x >= tk.ntiles) return;
+  if (threadIdx.x == 0) sh_tile = atomicAdd(&tk.st->ticket, 1u);
+  __syncthreads();
+  const uint32_t tile = sh_tile;
+  const bool failed = (__hip_atomic_load(&tk.st->too_wide, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+                       __hip_atomic_load(&tk.st->internal, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0u;
+  const long long p0 = static_cast<long long>(tile) * CARRY_TILE;
+  const uint32_t nout = tk.na + tk.nb;
+  const unsigned long long *c = tk.c;
+  const long long L = tk.L;
+  auto tc = [&](uint32_t G, uint32_t P) { return lookback(tk.tiles, tile, G, P, &tk.st->carry_err); };
+  if (bits == 8) {
+    auto C = [&](long long q) -> unsigned long long { return (q >= 0 && q < L) ? c[q] : 0ull; };
+    carry_block<CARRY_PER_THREAD>(C, p0, nout, tk.out, failed, tc, sh_waves);
+  } else {
+    auto C = [&](long long q) -> unsigned long long {
+      if (q < 0) return 0ull;
+      const long long i0 = 2 * q, i1 = 2 * q + 1;
+      return (i0 < L ? c[i0] : 0ull) + 16ull * (i1 < L ? c[i1] : 0ull);
+    };
+    carry_block<CARRY_PER_THREAD>(C, p0, nout, tk.out, failed, tc, sh_waves);
+  }
+}
+
+// Final status per product: 0 ok, 1 too wide, 4 device error, 5 internal.
+__global__ void k_status(const task *tasks, int ntasks, int *status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntasks) return;
+  const dev_stats *st = tasks[i].st;
+  int s = 0;
+  if (st->internal) s = 5;
+  else if (st->too_wide) s = 1;
+  else if (st->carry_err) s = 4;
+  status[i] = s;
+}
+
+// Directed-rounding probe: the primitives above on n inputs.
+// op 0: RU(a+b)  1: RU(a*b)  2: RU(a*b+c)  3: RD(a+b)  4: RD(a*b)  5: RD(a*b+c)
+__global__ void k_probe(int op, const double *a, const double *b, const double *c, double *out,
+                        size_t n) {
+  const uint32_t z = enter_round_up();
+  a = after_mode(a, z);
+  const size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const double x = a[i], y = b[i], w = c[i];
+  double r;
+  switch (op) {
+    case 0: r = ru_add(x, y); break;
+    case 1: r = ru_mul(x, y); break;
+    case 2: r = ru_fma(x, y, w); break;
+    case 3: r = -ru_add(-x, -y); break;
+    case 4: r = -ru_nmul(x, y); break;
+    default: r = -ru_fma(-x, y, -w); break;
+  }
+  out[i] = r;
+}
+
+// Statuses from batch slot order back to the caller's order.
+__global__ void k_scatter(const int *slot_status, const int *order, int n, int *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[order[i]] = slot_status[i];
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+
+static constexpr int MAX_DYN_LDS = 131072;
+
+hipError_t set_kernel_attributes() {
+  const void *ks[] = {reinterpret_cast<const void *>(&k_small),
+                      reinterpret_cast<const void *>(&k_col_fwd),
+                      reinterpret_cast<const void *>(&k_row),
+                      reinterpret_cast<const void *>(&k_col_inv)};
+  for (const void *k : ks) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, MAX_DYN_LDS);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_scatter_status(const int *slot_status, const int *order, int n, int *out,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, slot_status, order, n, out);
+  return hipGetLastError();
+}
+
+static twtab to_dev(const twtab_host &t) { return twtab{t.tab, t.log_ntab, t.e}; }
+
+hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bits, int cert_mode,
+                        const twtab_host &tw, double *dbg, hipStream_t s) {
+  const int threads = 1 << (log_n - 2);
+  const size_t lds = sizeof(ci) << log_n;
+  hipLaunchKernelGGL(k_small, dim3(ntasks), dim3(threads), lds, s, d_tasks, log_n, digit_bits,
+                     cert_mode, to_dev(tw), dbg);
+  return hipGetLastError();
+}
+
+hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const launch_cfg &cfg,
+                            int digit_bits, int cert_mode, const twtab_host &tw, double *dbg,
+                            hipStream_t s) {
+  const int l1 = cfg.log_n1, l2 = cfg.log_n2;
+  const uint32_t N1 = 1u << l1, N2 = 1u << l2;
+  const twtab T = to_dev(tw);
+  {
+    const int threads = cfg.cols * static_cast<int>(N1 / 4);
+    const size_t lds = sizeof(ci) * N1 * cfg.cols;
+    hipLaunchKernelGGL(k_col_fwd, dim3(N2 / cfg.cols, 2, ntasks), dim3(threads), lds, s, d_tasks,
+                       l1, l2, cfg.cols, digit_bits, T);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    const int threads = cfg.rows * static_cast<int>(N2 / 4);
+    const size_t lds = sizeof(ci) * N2 * cfg.rows;
+    hipLaunchKernelGGL(k_row, dim3(N1 / cfg.rows, ntasks), dim3(threads), lds, s, d_tasks, l1, l2,
+                       cfg.rows, T);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    const int threads = cfg.cols * static_cast<int>(N1 / 4);
+    const size_t lds = sizeof(ci) * N1 * cfg.cols;
+    hipLaunchKernelGGL(k_col_inv, dim3(N2 / cfg.cols, ntasks), dim3(threads), lds, s, d_tasks, l1,
+                       l2, cfg.cols, cert_mode, T, dbg);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  (void)log_n;
+  return hipSuccess;
+}
+
+hipError_t launch_carry(const task *d_tasks, int ntasks, uint32_t max_tiles, int digit_bits,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_carry, dim3(max_tiles, ntasks), dim3(CARRY_THREADS), 0, s, d_tasks,
+                     digit_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_status(const task *d_tasks, int ntasks, int *d_status, hipStream_t s) {
+  hipLaunchKernelGGL(k_status, dim3((ntasks + 255) / 256), dim3(256), 0, s, d_tasks, ntasks,
+                     d_status);
+  return hipGetLastError();
+}
+
+hipError_t launch_directed_probe(int op, const double *a, const double *b, const double *c,
+                                 double *out, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_probe, dim3((n + 255) / 256), dim3(256), 0, s, op, a, b, c, out, n);
+  return hipGetLastError();
+}
+
+}  // namespace ssa

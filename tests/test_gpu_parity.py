@@ -1,0 +1,344 @@
+"""GPU parity tests: the HIP library through its C ABI against the oracle.
+
+Products are integers, so the bar is bit-exact equality with the oracle's
+product and with CPython's integer product (and schoolbook / closed forms where
+they apply).  Enclosures are not unique; they are checked by containment of
+the exact coefficients, and the GPU's maximum radius is reported next to the
+oracle's.  Directed rounding is checked bit-for-bit against exact rationals.
+"""
+import math
+from fractions import Fraction
+
+import mpmath
+import numpy as np
+import pytest
+
+import oracle
+from paper_1006_0405_amd import binding
+from paper_1006_0405_amd.workloads import all_ff, batch, pair
+from pins import (all_ff_coefficients, all_ff_product, exact_convolution, int_product,
+                  long_multiplication, nibbles)
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _round_down(q):
+    f = float(q)
+    if Fraction(f) > q:
+        f = float(np.nextafter(f, -np.inf))
+    return f
+
+
+def _round_up(q):
+    f = float(q)
+    if Fraction(f) < q:
+        f = float(np.nextafter(f, np.inf))
+    return f
+
+
+# ---------------------------------------------------------------------------
+# Directed rounding primitives (section 2.5: outward rounding)
+
+
+def test_directed_rounding_bit_exact():
+    rng = np.random.default_rng(17)
+    n = 4000
+    a = rng.standard_normal(n) * np.exp2(rng.integers(-40, 40, n))
+    b = rng.standard_normal(n) * np.exp2(rng.integers(-40, 40, n))
+    c = rng.standard_normal(n) * np.exp2(rng.integers(-40, 40, n))
+    edge = np.array([0.0, -0.0, 1.0, -1.0, 0.5, 3.0, 1e-310, -1e-310, 5e-324, 2.0 ** 52,
+                     2.0 ** 53 - 1, 1.0 + 2.0 ** -52, 0.1, -0.7, 123456789.123, 1e-300])
+    a[:len(edge)] = edge
+    b[:len(edge)] = edge[::-1]
+    c[:len(edge)] = np.roll(edge, 3)
+    exact = {
+        0: lambda x, y, z: Fraction(x) + Fraction(y),
+        1: lambda x, y, z: Fraction(x) * Fraction(y),
+        2: lambda x, y, z: Fraction(x) * Fraction(y) + Fraction(z),
+    }
+    for op in range(6):
+        got = _np(binding.probe_directed(op, a, b, c))
+        f = exact[op % 3]
+        rnd = _round_up if op < 3 else _round_down
+        for i in range(n):
+            want = rnd(f(a[i], b[i], c[i]))
+            assert got[i] == want or (got[i] == 0 and want == 0), (op, a[i], b[i], c[i], got[i], want)
+
+
+# ---------------------------------------------------------------------------
+# Twiddles (section 2.2 recurrence, computed on the device)
+
+
+def _omega_iv(m, N):
+    m %= N
+    if (4 * m) % N == 0:
+        q = 4 * m // N
+        return [(mpmath.iv.mpf(x), mpmath.iv.mpf(y)) for x, y in [(1, 0), (0, 1), (-1, 0), (0, -1)]][q]
+    ang = 2 * mpmath.iv.pi * m / N
+    return mpmath.iv.cos(ang), mpmath.iv.sin(ang)
+
+
+@pytest.mark.parametrize("nbytes", [1000, 75000])
+def test_twiddle_table_encloses_roots_of_unity(nbytes):
+    plan = binding.Plan(nbytes, nbytes)
+    tab, e, lg = plan.twiddles()
+    plan.close()
+    tab = _np(tab)
+    N = 1 << lg
+    # half an ulp of the stored midpoint plus the fixed-point enclosure width
+    # (about 2^-62 per exact product over the set bits of t): below one ulp of 1
+    print("twiddle table 2^%d: e = %.3e" % (lg, e))
+    assert 0 < e < 1.2e-16
+    mpmath.iv.prec = 200
+    idx = sorted(set([0, 1, N // 8, N // 4, N // 2, N - 1] + list(range(0, N, max(1, N // 700)))))
+    for t in idx:
+        cs, sn = _omega_iv(t, N)
+        for val, iv in ((tab[t, 0], cs), (tab[t, 1], sn)):
+            lo, hi = mpmath.mpf(val) - mpmath.mpf(e), mpmath.mpf(val) + mpmath.mpf(e)
+            assert lo <= iv.a and iv.b <= hi, (t, val, iv, e)
+
+
+# ---------------------------------------------------------------------------
+# Single products
+
+
+def _check_product(plan, a, b, digit_bits=8, with_oracle=True):
+    st, out = plan.mul(a, b)
+    out = _np(out)
+    assert st == binding.SSA_OK, binding.STATUS_NAMES.get(st, st)
+    assert np.array_equal(out, int_product(a, b))
+    if with_oracle:
+        ost, oout, orad, _ = oracle.mul(a, b, digit_bits=digit_bits)
+        assert ost == oracle.ST_OK
+        assert np.array_equal(out, oout)
+    return out
+
+
+def test_tiny_products():
+    from test_oracle import read_tiny_products
+    plan = binding.Plan(8, 8)
+    for a, b, c, z in read_tiny_products():
+        st, out = plan.mul(a, b)
+        assert st == binding.SSA_OK
+        assert _np(out).tolist() == z.tolist()
+    plan.close()
+
+
+@pytest.mark.parametrize("digit_bits", [8, 4])
+def test_small_path_ragged_sizes(digit_bits):
+    plan = binding.Plan(2048, 2048, digit_bits=digit_bits)
+    sizes = [(1, 1), (1, 2), (2, 1), (3, 5), (17, 33), (64, 65), (127, 2), (128, 129), (200, 57),
+             (255, 256), (511, 512), (1000, 1), (1023, 1025), (2048, 2048), (1500, 300)]
+    for s, (na, nb) in enumerate(sizes):
+        if digit_bits == 4 and na + nb > 2049:
+            continue
+        a, b = pair(500 + s, na, nb)
+        _check_product(plan, a, b, digit_bits)
+    plan.close()
+
+
+def test_leading_zeros_and_zero_operands():
+    plan = binding.Plan(300, 300)
+    rng = np.random.default_rng(3)
+    a = rng.integers(0, 256, 300, dtype=np.uint8)
+    a[-40:] = 0
+    z = np.zeros(100, np.uint8)
+    for x, y in [(a, z), (z, a), (a, a), (z, z)]:
+        _check_product(plan, x, y)
+    plan.close()
+
+
+def test_config1_product_vs_oracle_and_schoolbook():
+    a, b = pair(1, 1024)
+    plan = binding.Plan(1024, 1024)
+    out = _check_product(plan, a, b)
+    assert np.array_equal(out, long_multiplication(a, b))
+    rad = plan.stats()["max_radius"]
+    _, _, orad, _ = oracle.mul(a, b)
+    print("config1: GPU max radius %.3e, oracle %.3e" % (rad, orad))
+    assert 0 < rad < 0.5
+    plan.close()
+
+
+@pytest.mark.parametrize("na,nb,digit_bits", [(1, 1, 8), (300, 200, 8), (1024, 1024, 8),
+                                              (2048, 2047, 8), (3000, 2500, 8), (5000, 9000, 8),
+                                              (16000, 16384, 8), (700, 900, 4), (9000, 7000, 4)])
+def test_enclosures_contain_exact_coefficients(na, nb, digit_bits):
+    a, b = pair(na * 7 + nb, na, nb)
+    plan = binding.Plan(na, nb, digit_bits=digit_bits)
+    st, out, enc = plan.debug_enclosures(a, b)
+    enc = _np(enc)
+    assert st == binding.SSA_OK
+    assert np.array_equal(_np(out), int_product(a, b))
+    if digit_bits == 8:
+        c = exact_convolution(a, b)
+    else:
+        c = exact_convolution(nibbles(a), nibbles(b))
+    L = len(c)
+    assert np.all(enc[:, 0] <= enc[:, 1]) and np.all(enc[:, 2] <= enc[:, 3])
+    assert np.all(enc[:L, 0] <= c) and np.all(c <= enc[:L, 1])
+    assert np.all(enc[:, 2] <= 0) and np.all(enc[:, 3] >= 0)
+    assert np.all(enc[L:, 0] <= 0) and np.all(enc[L:, 1] >= 0)
+    plan.close()
+
+
+@pytest.mark.parametrize("na,nb", [(2049, 2048), (4096, 4096), (6000, 3000), (8192, 8192),
+                                   (16384, 16384), (20000, 12000)])
+def test_multipass_products_vs_oracle(na, nb):
+    a, b = pair(na + 3 * nb, na, nb)
+    plan = binding.Plan(na, nb)
+    _check_product(plan, a, b)
+    plan.close()
+
+
+@pytest.mark.parametrize("n,m", [(2049, 2049), (8192, 100), (40000, 40000)])
+def test_all_ff_multipass(n, m):
+    plan = binding.Plan(n, m)
+    st, out = plan.mul(all_ff(n), all_ff(m))
+    assert st == binding.SSA_OK
+    assert np.array_equal(_np(out), all_ff_product(n, m))
+    plan.close()
+
+
+def test_config2_random_and_all_ff():
+    n = 75000
+    plan = binding.Plan(n, n)
+    a, b = pair(2, n)
+    st, out = plan.mul(a, b)
+    out = _np(out)
+    rad = plan.stats()["max_radius"]
+    assert st == binding.SSA_OK
+    assert np.array_equal(out, int_product(a, b))
+    ost, oout, orad, _ = oracle.mul(a, b)
+    assert ost == oracle.ST_OK and np.array_equal(out, oout)
+    print("config2 random: GPU max radius %.4f, oracle %.4f" % (rad, orad))
+    f = all_ff(n)
+    st, out = plan.mul(f, f)
+    assert st == binding.SSA_OK
+    assert np.array_equal(_np(out), all_ff_product(n, n))
+    print("config2 all-0xFF: GPU max radius %.4f" % plan.stats()["max_radius"])
+    plan.close()
+
+
+def test_config5_base16_random_and_all_ff():
+    n = 1_000_000
+    plan = binding.Plan(n, n, digit_bits=4)
+    a, b = pair(5, n)
+    st, out = plan.mul(a, b)
+    assert st == binding.SSA_OK, binding.STATUS_NAMES.get(st, st)
+    assert _np(out).tobytes() == (int.from_bytes(a.tobytes(), "little") *
+                                  int.from_bytes(b.tobytes(), "little")).to_bytes(2 * n, "little")
+    print("config5 random: GPU max radius %.4f, log_n %d" % (plan.stats()["max_radius"],
+                                                              plan.stats()["log_n"]))
+    f = all_ff(n)
+    st, out = plan.mul(f, f)
+    assert st == binding.SSA_OK
+    assert np.array_equal(_np(out), all_ff_product(n, n))
+    print("config5 all-0xFF: GPU max radius %.4f" % plan.stats()["max_radius"])
+    plan.close()
+
+
+def test_config5_enclosures_contain_sampled_coefficients():
+    n = 1_000_000
+    plan = binding.Plan(n, n, digit_bits=4)
+    a, b = pair(5, n)
+    st, _, enc = plan.debug_enclosures(a, b)
+    assert st == binding.SSA_OK
+    x = nibbles(a).astype(np.int64)
+    y = nibbles(b).astype(np.int64)
+    L = len(x) + len(y) - 1
+    rng = np.random.default_rng(0)
+    idx = np.concatenate([[0, 1, L // 2, L - 2, L - 1], rng.integers(0, L, 1000)])
+    enc_np = _np(enc[torch_index(idx)])
+    for k, i in enumerate(idx):
+        j0, j1 = max(0, i - len(y) + 1), min(len(x) - 1, i)
+        ci = int(np.dot(x[j0:j1 + 1], y[i - j1:i - j0 + 1][::-1]))
+        assert enc_np[k, 0] <= ci <= enc_np[k, 1], (i, ci, enc_np[k])
+    plan.close()
+
+
+def torch_index(idx):
+    import torch
+    return torch.as_tensor(np.asarray(idx, dtype=np.int64), device="cuda")
+
+
+def test_determinism():
+    a, b = pair(77, 30000, 29000)
+    plan = binding.Plan(30000, 29000)
+    outs, rads = [], []
+    for _ in range(3):
+        st, out = plan.mul(a, b)
+        assert st == binding.SSA_OK
+        outs.append(_np(out))
+        rads.append(plan.stats()["max_radius"])
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+    assert rads[0] == rads[1] == rads[2]
+    plan.close()
+
+
+def test_invalid_arguments():
+    plan = binding.Plan(100, 100)
+    with pytest.raises(binding.SsaError):
+        plan.mul(np.zeros(0, np.uint8), np.ones(3, np.uint8))
+    with pytest.raises(binding.SsaError):
+        plan.mul(np.ones(101, np.uint8), np.ones(3, np.uint8))
+    plan.close()
+    with pytest.raises(binding.SsaError):
+        binding.Plan(0, 10)
+
+
+def test_strict_half_integer_mode_never_wrong():
+    plan = binding.Plan(5000, 5000, certify_mode=binding.SSA_CERTIFY_HALF_INTEGER)
+    for s in range(4):
+        a, b = pair(900 + s, 5000)
+        st, out = plan.mul(a, b)
+        assert st in (binding.SSA_OK, binding.SSA_ENCLOSURE_TOO_WIDE)
+        if st == binding.SSA_OK:
+            assert np.array_equal(_np(out), int_product(a, b))
+        else:
+            assert not _np(out).any()
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Batches
+
+
+def test_batch_mixed_lengths():
+    rng = np.random.default_rng(21)
+    A, B = [], []
+    for i in range(300):
+        na = int(rng.integers(1, 12000))
+        nb = int(rng.integers(1, 12000))
+        a, b = pair(10_000 + i, na, nb)
+        A.append(a)
+        B.append(b)
+    plan = binding.Plan(12000, 12000)
+    bt = binding.Batch(plan, A, B)
+    for rep in range(2):
+        status = _np(bt.run())
+        assert np.all(status == binding.SSA_OK)
+        for i in range(len(A)):
+            assert np.array_equal(_np(bt.OUT[i]), int_product(A[i], B[i])), i
+    st = bt.stats()
+    assert all(s["status"] == 0 for s in st)
+    bt.close()
+    plan.close()
+
+
+def test_config3_batch_full():
+    A, B = batch(seed=3)
+    plan = binding.Plan(16384, 16384)
+    bt = binding.Batch(plan, A, B)
+    status = _np(bt.run())
+    assert np.all(status == binding.SSA_OK)
+    for i in range(len(A)):
+        assert np.array_equal(_np(bt.OUT[i]), int_product(A[i], B[i])), i
+    rads = [s["max_radius"] for s in bt.stats()]
+    print("config3: %d products, max radius %.4f" % (len(A), max(rads)))
+    bt.close()
+    plan.close()
