@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Throughput of the rigorous interval Schoenhage-Strassen product on one MI355X.
+
+Workload: products of two 75,000-digit base-256 integers, transform length
+N = 2^18, FP64 rectangular intervals.  Half the products use uniform random
+bytes (seeded, top byte non-zero), half use all-0xFF operands (the largest
+coefficients).  A step is one pass of the whole path (two forward interval
+FFTs, pointwise product, inverse FFT, certification, carries) over a batch of
+such products whose operands are already resident in device memory.
+
+Prints one JSON line: certified products/s, the roofline of the dominant
+kernel measured with HIP events around its launches in the timed region, and
+the CPU oracle timed on the host's cores on a bounded sample.
+"""
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "certified products/s & HBM GB/s: FP64 interval vs FP32+fallback, 2^18 FFT"
+UNIT = "certified products/s"
+NBYTES = 75_000
+HBM_PEAK_GBPS = 8000.0
+ELEM = 32  # bytes of one FP64 rectangular complex interval
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1006_0405_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def alg_bytes_per_product(kind, N, L, nbytes_total, packed=True):
+    """Algorithmic HBM bytes one product needs in each kernel: every FP64
+    interval array element read or written once is 32 bytes.  Packed: one
+    transformed array (a + i b); separate: one array per operand."""
+    arrays = 1 if packed else 2
+    return {
+        "col_fwd": arrays * N * ELEM + nbytes_total,   # read digits, write the column-transformed array(s)
+        "row": (arrays + 1) * N * ELEM,                # read the array(s), write the inverse-half result
+        "col_inv": N * ELEM + 8 * L,                   # read it, write the certified int64 coefficients
+        "carry": 8 * L + nbytes_total,                 # read coefficients, write the product bytes
+    }[kind]
+
+
+def _cpu_worker(args):
+    kind, seed = args
+    import oracle
+    from paper_1006_0405_amd.workloads import all_ff, pair
+    if kind == "ff":
+        a = b = all_ff(NBYTES)
+    else:
+        a, b = pair(seed, NBYTES)
+    t0 = time.perf_counter()
+    st, _, rad, _ = oracle.mul(a, b)
+    return st, time.perf_counter() - t0
+
+
+def cpu_baseline(nworkers):
+    import multiprocessing as mp
+    import oracle
+    oracle.lib()  # build once in the parent if needed
+    jobs = [("ff" if i % 2 else "rand", 2 + i // 2) for i in range(nworkers)]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(nworkers) as pool:
+        res = pool.map(_cpu_worker, jobs)
+    wall = time.perf_counter() - t0
+    ok = sum(1 for st, _ in res if st == 0)
+    cpu_s = sum(t for _, t in res)
+    return {
+        "value": ok / wall,
+        "unit": UNIT,
+        "cores": nworkers,
+        "kind": "oracle",
+        "sample": "%d products of 75,000 x 75,000 bytes (N = 2^18; half uniform random, half "
+                  "all-0xFF), one per process, %.1f s of oracle CPU time over %.1f s wall; "
+                  "%d certified" % (len(jobs), cpu_s, wall, ok),
+    }
+
+
+def traffic_for(kernel, launches_products):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("source_hash") != kernel_source_hash() or kernel not in d.get("kernels", {}):
+        return None
+    k = d["kernels"][kernel]
+    per_product = k["bytes_per_product"]
+    return per_product * launches_products
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=64, help="products per step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--separate-transforms", action="store_true",
+                    help="one forward FFT per operand (the fast convolution box literally) "
+                         "instead of one FFT of a + i b")
+    ap.add_argument("--cpu-workers", type=int, default=0, help="0 = min(16, host cores)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (torch), the reference "
+                         "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings")
+    ap.add_argument("--latency", action="store_true",
+                    help="also time single products through ssa_mul (separate launches of the "
+                         "same kernels, so leave it off when profiling per-kernel averages)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the path has no multi-GPU component in this "
+              "build (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.copy_calibration:
+        n = 1 << 30
+        x = torch.ones(n, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "launches": 3}), flush=True)
+        return
+    from paper_1006_0405_amd import binding
+    from paper_1006_0405_amd.workloads import all_ff, pair
+
+    B = args.batch
+    A, Bs = [], []
+    for i in range(B):
+        if i % 2:
+            A.append(all_ff(NBYTES))
+            Bs.append(all_ff(NBYTES))
+        else:
+            a, b = pair(2 + i // 2, NBYTES)
+            A.append(a)
+            Bs.append(b)
+    N = binding.fft_size(NBYTES, NBYTES)
+    L = 2 * NBYTES - 1
+    packed = not args.separate_transforms
+    plan = binding.Plan(NBYTES, NBYTES, separate_transforms=not packed)
+    batch = binding.Batch(plan, A, Bs)
+
+    # correctness of the timed work, checked once outside the timed region
+    status = batch.run().cpu().numpy()
+    assert np.all(status == binding.SSA_OK), status
+    for i in range(B):
+        got = batch.OUT[i].cpu().numpy().tobytes()
+        want = (int.from_bytes(A[i].tobytes(), "little") *
+                int.from_bytes(Bs[i].tobytes(), "little")).to_bytes(2 * NBYTES, "little")
+        assert got == want, "product %d is wrong" % i
+    max_rad = max(s["max_radius"] for s in batch.stats())
+
+    for _ in range(args.warmup):
+        batch.run_timed()
+    torch.cuda.synchronize()
+    batch.kernel_times()  # discard warm-up timings
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run_timed()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ktimes = batch.kernel_times()
+    status = batch.status.cpu().numpy()
+    certified = int(np.sum(status == binding.SSA_OK)) * args.steps
+    value = certified / elapsed
+
+    # the same steps through the captured graph (one launch per step)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run()
+    torch.cuda.synchronize()
+    graph_rate = B * args.steps / (time.perf_counter() - g0)
+
+    latency_ms = None
+    if args.latency:  # single-product latency through ssa_mul (includes its host sync)
+        a0, b0 = pair(2, NBYTES)
+        da = torch.from_numpy(a0).cuda()
+        db = torch.from_numpy(b0).cuda()
+        lat = []
+        for _ in range(12):
+            t = time.perf_counter()
+            st, _ = plan.mul(da, db)
+            lat.append(time.perf_counter() - t)
+            assert st == binding.SSA_OK
+        latency_ms = float(np.median(lat[2:]) * 1e3)
+
+    kinds = ["col_fwd", "row", "col_inv", "carry"]
+    per_launch_ms = {k: ktimes[k][0] / max(ktimes[k][1], 1) for k in kinds}
+    dom = max(kinds, key=lambda k: ktimes[k][0])
+    bytes_launch = alg_bytes_per_product(dom, N, L, 2 * NBYTES, packed) * B
+    achieved = bytes_launch / (per_launch_ms[dom] * 1e-3) / 1e9
+    step_bytes = sum(alg_bytes_per_product(k, N, L, 2 * NBYTES, packed) for k in kinds) * B
+    traffic = traffic_for(dom, B)
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "75,000 x 75,000-byte products, N = 2^18, FP64 rectangular intervals; "
+                        "half uniform random bytes, half all-0xFF",
+            "batch": B,
+            "operand_bytes": NBYTES,
+            "fft_length": N,
+            "digit_bits": 8,
+            "transform": "one complex FFT of a + i b" if packed else "one FFT per operand",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": traffic,
+            "alg_bytes_per_launch": bytes_launch,
+            "ms_per_launch": per_launch_ms[dom],
+        },
+        "digits_per_s": value * 2 * NBYTES,
+        "alg_GBps_whole_step": step_bytes / (elapsed / args.steps) / 1e9,
+        "kernel_ms_per_launch": per_launch_ms,
+        "graph_products_per_s": graph_rate,
+        "single_product_latency_ms": latency_ms,
+        "max_radius": max_rad,
+        "context": "paper: FP64 interval SSA usually certifies up to 75,000 base-256 digits "
+                   "(2.2 GHz Athlon 64 3500+, C-XSC 2.2.4, single thread)",
+    }
+    batch.close()
+    plan.close()
+
+    if not args.no_cpu_baseline:
+        n = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
+        result["cpu_baseline"] = cpu_baseline(n)
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

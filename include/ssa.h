@@ -56,7 +56,11 @@ typedef struct {
   int certify_mode;        /* SSA_CERTIFY_ONE_INTEGER: exactly one integer (section 1);
                               SSA_CERTIFY_HALF_INTEGER: additionally fail any enclosure
                               that contains a half-integer (stricter)                 */
-  int reserved;
+  int separate_transforms; /* 0 (default): both real operands go through ONE complex
+                              interval FFT of a + i b and are separated afterwards
+                              (A_k = (Z_k + conj Z_{-k})/2, B_k = (Z_k - conj Z_{-k})/2i);
+                              1: one forward FFT per operand, as in the fast
+                              convolution box of section 2.3.  Same products.       */
 } ssa_plan_opts;
 
 typedef struct {
@@ -113,6 +117,17 @@ ssa_status ssa_batch_run(ssa_batch *batch, int *status_dev);
 /* Per-product statistics of the last run (host array of `count`); synchronises. */
 ssa_status ssa_batch_stats(ssa_batch *batch, ssa_stats *stats_host);
 void ssa_batch_destroy(ssa_batch *batch);
+
+/* Run a batch without its graph, with a HIP event recorded on the plan's
+ * stream right before and right after every kernel launch (for timing). */
+ssa_status ssa_batch_run_timed(ssa_batch *batch, int *status_dev);
+/* Kernel time of the timed runs since the previous call, summed per kernel
+ * kind into ms_host[6] (milliseconds) with the launch counts in
+ * launches_host[6]: 0 single-workgroup product, 1 forward column pass,
+ * 2 row pass (forward rows, pointwise product, inverse rows), 3 inverse
+ * column pass with scaling and certification, 4 carry scan, 5 status.
+ * Synchronises the plan's stream. */
+ssa_status ssa_batch_kernel_times(ssa_batch *batch, double *ms_host, int *launches_host);
 
 /* Convenience: create, run, synchronise, destroy. */
 ssa_status ssa_mul_batch(ssa_plan *plan, size_t count, const uint8_t *const *a, const size_t *na,

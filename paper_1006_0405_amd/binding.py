@@ -31,7 +31,9 @@ SSA_CERTIFY_HALF_INTEGER = 1
 # Every entry point declared in include/ssa.h.
 EXPORTS = ("ssa_fft_size", "ssa_plan_create", "ssa_plan_destroy", "ssa_mul", "ssa_get_stats",
            "ssa_batch_create", "ssa_batch_run", "ssa_batch_stats", "ssa_batch_destroy",
-           "ssa_mul_batch", "ssa_debug_enclosures", "ssa_twiddle_table", "ssa_probe_directed")
+           "ssa_mul_batch", "ssa_debug_enclosures", "ssa_twiddle_table", "ssa_probe_directed",
+           "ssa_batch_run_timed", "ssa_batch_kernel_times")
+KERNEL_KINDS = ("small", "col_fwd", "row", "col_inv", "carry", "status")
 
 
 class SsaError(RuntimeError):
@@ -40,7 +42,7 @@ class SsaError(RuntimeError):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("digit_bits", ctypes.c_int),
-                ("certify_mode", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("certify_mode", ctypes.c_int), ("separate_transforms", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -84,6 +86,10 @@ def lib():
         L.ssa_batch_stats.argtypes = [_vp, _vp]
         L.ssa_batch_destroy.restype = None
         L.ssa_batch_destroy.argtypes = [_vp]
+        L.ssa_batch_run_timed.restype = ctypes.c_int
+        L.ssa_batch_run_timed.argtypes = [_vp, _vp]
+        L.ssa_batch_kernel_times.restype = ctypes.c_int
+        L.ssa_batch_kernel_times.argtypes = [_vp, _vp, _vp]
         L.ssa_mul_batch.restype = ctypes.c_int
         L.ssa_mul_batch.argtypes = [_vp, _sz, _vp, _vp, _vp, _vp, _vp, _vp]
         L.ssa_debug_enclosures.restype = ctypes.c_int
@@ -128,11 +134,11 @@ class Plan:
     """A plan for products with at most max_na x max_nb bytes."""
 
     def __init__(self, max_na, max_nb, digit_bits=8, certify_mode=SSA_CERTIFY_ONE_INTEGER,
-                 stream=None, device=None):
+                 separate_transforms=False, stream=None, device=None):
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.digit_bits = digit_bits
-        opts = PlanOpts(SSA_FP64, digit_bits, certify_mode, 0)
+        opts = PlanOpts(SSA_FP64, digit_bits, certify_mode, int(bool(separate_transforms)))
         h = _vp()
         with torch.cuda.device(self.device):
             _check(lib().ssa_plan_create(ctypes.byref(h), max_na, max_nb, ctypes.byref(opts),
@@ -221,6 +227,19 @@ class Batch:
     def run(self):
         _check(lib().ssa_batch_run(self.handle, self.status.data_ptr()), "ssa_batch_run")
         return self.status
+
+    def run_timed(self):
+        """Run without the graph, with HIP events around every kernel."""
+        _check(lib().ssa_batch_run_timed(self.handle, self.status.data_ptr()), "ssa_batch_run_timed")
+        return self.status
+
+    def kernel_times(self):
+        """{kind: (total ms, launches)} of the timed runs since the last call."""
+        ms = (ctypes.c_double * 6)()
+        n = (ctypes.c_int * 6)()
+        _check(lib().ssa_batch_kernel_times(self.handle, ctypes.cast(ms, _vp), ctypes.cast(n, _vp)),
+               "ssa_batch_kernel_times")
+        return {KERNEL_KINDS[k]: (ms[k], n[k]) for k in range(6)}
 
     def stats(self):
         arr = (Stats * self.count)()

@@ -19,7 +19,7 @@ using namespace ssa;
 
 namespace {
 
-constexpr int MAX_LOG_N = 23;  // column pass: N1 <= 2^11 (1024 threads)
+constexpr int MAX_LOG_N = 22;  // N1 = N2 = 2^11: 1024-thread column and 512-thread row passes
 
 int ceil_log2(uint64_t v) {
   int k = 0;
@@ -33,13 +33,17 @@ int log_n_for(uint64_t L) { return std::max(ceil_log2(L), SMALL_MIN_LOG); }
 uint64_t digits(size_t n, int bits) { return bits == 4 ? 2 * uint64_t(n) : uint64_t(n); }
 
 // Default launch shape of the three-pass path for N = 2^log_n.
-launch_cfg default_cfg(int log_n) {
+launch_cfg default_cfg(int log_n, int pack) {
   launch_cfg c;
   c.log_n1 = log_n / 2;
   c.log_n2 = log_n - c.log_n1;
   const int N1 = 1 << c.log_n1, N2 = 1 << c.log_n2;
   c.cols = std::max(2, std::min(16, 2048 / N1));
-  c.rows = std::max(1, std::min(8, 1024 / N2));
+  c.pack = pack;
+  if (pack)  // row pairs: one LDS row per pair, at most 512 threads
+    c.rows = std::max(1, std::min(N1 / 2, 1024 / N2));
+  else
+    c.rows = std::max(1, std::min(8, 1024 / N2));
   return c;
 }
 
@@ -112,6 +116,13 @@ struct ssa_batch {
   int *d_order = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  uint32_t max_tiles = 0;
+  size_t n_multi = 0;
+  // timed (eager) runs: one event before and one after every kernel launch
+  std::vector<hipEvent_t> events;
+  std::vector<int> kinds;
+  size_t ev_used = 0;
+  bool ev_error = false;
 };
 
 namespace {
@@ -138,8 +149,10 @@ twtab_host tw_of(const ssa_plan *p) { return twtab_host{p->tab, p->log_ntab, p->
 hipError_t enqueue_class(const ssa_plan *p, const task *d_tasks, int n, int log_n, double *dbg,
                          hipStream_t s) {
   const int bits = p->opts.digit_bits, mode = p->opts.certify_mode;
-  if (log_n <= SMALL_MAX_LOG) return launch_small(d_tasks, n, log_n, bits, mode, tw_of(p), dbg, s);
-  return launch_multipass(d_tasks, n, log_n, default_cfg(log_n), bits, mode, tw_of(p), dbg, s);
+  const int pack = p->opts.separate_transforms ? 0 : 1;
+  if (log_n <= SMALL_MAX_LOG)
+    return launch_small(d_tasks, n, log_n, bits, mode, pack, tw_of(p), dbg, s);
+  return launch_multipass(d_tasks, n, log_n, default_cfg(log_n, pack), bits, mode, tw_of(p), dbg, s);
 }
 
 ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
@@ -195,11 +208,11 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
                            const ssa_plan_opts *opts, void *stream) {
   if (!plan) return SSA_INVALID_ARGUMENT;
   *plan = nullptr;
-  ssa_plan_opts o{SSA_FP64, 8, SSA_CERTIFY_ONE_INTEGER, 0};
+  ssa_plan_opts o{SSA_FP64, 8, SSA_CERTIFY_ONE_INTEGER, 0};  // packed transform
   if (opts) o = *opts;
   if (max_na == 0 || max_nb == 0 || (o.digit_bits != 8 && o.digit_bits != 4) ||
       (o.certify_mode != SSA_CERTIFY_ONE_INTEGER && o.certify_mode != SSA_CERTIFY_HALF_INTEGER) ||
-      o.precision != SSA_FP64)
+      o.precision != SSA_FP64 || (o.separate_transforms != 0 && o.separate_transforms != 1))
     return SSA_INVALID_ARGUMENT;
   const uint64_t L = digits(max_na, o.digit_bits) + digits(max_nb, o.digit_bits) - 1;
   const int log_nmax = log_n_for(L);
@@ -224,7 +237,7 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
             hip_ok(hipMalloc(&p->roots, twiddle_roots_bytes())) &&
             hip_ok(hipMalloc(&p->c, sizeof(unsigned long long) * N)) &&
             hip_ok(hipMalloc(&p->st, sizeof(dev_stats))) &&
-            hip_ok(hipMalloc(&p->tiles, sizeof(uint32_t) * ntiles)) &&
+            hip_ok(hipMalloc(&p->tiles, sizeof(uint32_t) * TILE_WORD_STRIDE * ntiles)) &&
             hip_ok(hipMalloc(&p->d_task, sizeof(task))) &&
             hip_ok(hipHostMalloc(&p->h_task, sizeof(task), hipHostMallocDefault)) &&
             hip_ok(hipHostMalloc(&p->h_stats, sizeof(dev_stats), hipHostMallocDefault));
@@ -301,6 +314,7 @@ ssa_status ssa_probe_directed(int op, const double *a, const double *b, const do
 void ssa_batch_destroy(ssa_batch *bt) {
   if (!bt) return;
   if (bt->plan) hipStreamSynchronize(bt->plan->stream);
+  for (hipEvent_t ev : bt->events) hipEventDestroy(ev);
   if (bt->exec) hipGraphExecDestroy(bt->exec);
   if (bt->graph) hipGraphDestroy(bt->graph);
   hipFree(bt->d_tasks);
@@ -321,6 +335,54 @@ namespace ssa {
 hipError_t launch_scatter_status(const int *slot_status, const int *order, int n, int *out,
                                  hipStream_t s);
 }
+
+namespace {
+
+// Per length class one launch (or three), then one carry scan over every
+// multi-pass product, then the statuses.
+hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk) {
+  const ssa_plan *p = bt->plan;
+  const int bits = p->opts.digit_bits, mode = p->opts.certify_mode;
+  size_t s0 = 0;
+  const size_t count = bt->count;
+  while (s0 < count) {
+    size_t s1 = s0;
+    const int l = static_cast<int>(bt->h_tasks[s0].log_n);
+    while (s1 < count && static_cast<int>(bt->h_tasks[s1].log_n) == l) ++s1;
+    const int n = static_cast<int>(s1 - s0);
+    const int pack = p->opts.separate_transforms ? 0 : 1;
+    hipError_t e = l <= SMALL_MAX_LOG
+                       ? launch_small(bt->d_tasks + s0, n, l, bits, mode, pack, tw_of(p), nullptr, s, hk)
+                       : launch_multipass(bt->d_tasks + s0, n, l, default_cfg(l, pack), bits, mode,
+                                          tw_of(p), nullptr, s, hk);
+    if (e != hipSuccess) return e;
+    s0 = s1;
+  }
+  if (bt->n_multi) {
+    hipError_t e = launch_carry(bt->d_tasks, static_cast<int>(bt->n_multi), bt->max_tiles, bits, s, hk);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = launch_status(bt->d_tasks, static_cast<int>(count), bt->d_status_slot, s, hk);
+  if (e != hipSuccess) return e;
+  return launch_scatter_status(bt->d_status_slot, bt->d_order, static_cast<int>(count),
+                               bt->d_status, s);
+}
+
+void mark_event(void *ctx, int kind, int phase) {
+  ssa_batch *bt = static_cast<ssa_batch *>(ctx);
+  if (bt->ev_used == bt->events.size()) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreate(&ev) != hipSuccess) {
+      bt->ev_error = true;
+      return;
+    }
+    bt->events.push_back(ev);
+  }
+  if (phase == 0) bt->kinds.push_back(kind);
+  if (hipEventRecord(bt->events[bt->ev_used++], bt->plan->stream) != hipSuccess) bt->ev_error = true;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -366,7 +428,7 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
   if (ok && arena_elems)
     ok = hip_ok(hipMalloc(&bt->arena, sizeof(ci) * arena_elems)) &&
          hip_ok(hipMalloc(&bt->carena, sizeof(unsigned long long) * c_elems)) &&
-         hip_ok(hipMalloc(&bt->tiles, sizeof(uint32_t) * std::max<size_t>(tiles, 1)));
+         hip_ok(hipMalloc(&bt->tiles, sizeof(uint32_t) * TILE_WORD_STRIDE * std::max<size_t>(tiles, 1)));
   if (!ok) {
     ssa_batch_destroy(bt);
     hipGetLastError();
@@ -396,7 +458,7 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
       t.c = bt->carena + co;
       co += N;
       t.ntiles = static_cast<uint32_t>((na[i] + nb[i] + CARRY_TILE - 1) / CARRY_TILE);
-      t.tiles = bt->tiles + to;
+      t.tiles = bt->tiles + to * TILE_WORD_STRIDE;
       to += t.ntiles;
     }
   }
@@ -410,28 +472,16 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
     ssa_batch_destroy(bt);
     return SSA_DEVICE_ERROR;
   }
-  // Capture: per length class one launch (or three), then one carry scan over
-  // every multi-pass product, then the status scatter.
+  for (size_t k = 0; k < count; ++k)
+    if (bt->h_tasks[k].log_n > static_cast<uint32_t>(SMALL_MAX_LOG)) {
+      bt->n_multi = k + 1;  // multi-pass classes come first
+      bt->max_tiles = std::max(bt->max_tiles, bt->h_tasks[k].ntiles);
+    }
+  // Capture the launch sequence into one graph.
   hipStream_t cs = nullptr;
   ok = hip_ok(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   if (ok) ok = hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  size_t s0 = 0;
-  uint32_t max_tiles = 0;
-  size_t n_multi = 0;
-  while (ok && s0 < count) {
-    size_t s1 = s0;
-    const int l = static_cast<int>(bt->h_tasks[s0].log_n);
-    while (s1 < count && static_cast<int>(bt->h_tasks[s1].log_n) == l) {
-      max_tiles = std::max(max_tiles, bt->h_tasks[s1].ntiles);
-      ++s1;
-    }
-    if (l > SMALL_MAX_LOG) n_multi = s1;  // multi-pass classes come first
-    ok = hip_ok(enqueue_class(plan, bt->d_tasks + s0, static_cast<int>(s1 - s0), l, nullptr, cs));
-    s0 = s1;
-  }
-  if (ok && n_multi) ok = hip_ok(launch_carry(bt->d_tasks, static_cast<int>(n_multi), max_tiles, bits, cs));
-  if (ok) ok = hip_ok(launch_status(bt->d_tasks, static_cast<int>(count), bt->d_status_slot, cs));
-  if (ok) ok = hip_ok(launch_scatter_status(bt->d_status_slot, bt->d_order, static_cast<int>(count), bt->d_status, cs));
+  if (ok) ok = hip_ok(enqueue_batch(bt, cs, nullptr));
   hipGraph_t g = nullptr;
   if (cs) {
     const hipError_t ec = hipStreamEndCapture(cs, &g);
@@ -460,6 +510,37 @@ ssa_status ssa_batch_run(ssa_batch *bt, int *status_dev) {
   if (!hip_ok(hipMemcpyAsync(status_dev, bt->d_status, sizeof(int) * bt->count,
                              hipMemcpyDeviceToDevice, s)))
     return SSA_DEVICE_ERROR;
+  return SSA_OK;
+}
+
+ssa_status ssa_batch_run_timed(ssa_batch *bt, int *status_dev) {
+  if (!bt || !status_dev) return SSA_INVALID_ARGUMENT;
+  hipStream_t s = bt->plan->stream;
+  timing_hook hk{mark_event, bt};
+  if (!hip_ok(enqueue_batch(bt, s, &hk)) || bt->ev_error) return SSA_DEVICE_ERROR;
+  if (!hip_ok(hipMemcpyAsync(status_dev, bt->d_status, sizeof(int) * bt->count,
+                             hipMemcpyDeviceToDevice, s)))
+    return SSA_DEVICE_ERROR;
+  return SSA_OK;
+}
+
+ssa_status ssa_batch_kernel_times(ssa_batch *bt, double *ms_host, int *launches_host) {
+  if (!bt || !ms_host || !launches_host) return SSA_INVALID_ARGUMENT;
+  for (int k = 0; k < KIND_COUNT; ++k) {
+    ms_host[k] = 0.0;
+    launches_host[k] = 0;
+  }
+  if (!hip_ok(hipStreamSynchronize(bt->plan->stream))) return SSA_DEVICE_ERROR;
+  for (size_t i = 0; i < bt->kinds.size(); ++i) {
+    float ms = 0.f;
+    if (!hip_ok(hipEventElapsedTime(&ms, bt->events[2 * i], bt->events[2 * i + 1])))
+      return SSA_DEVICE_ERROR;
+    ms_host[bt->kinds[i]] += ms;
+    launches_host[bt->kinds[i]] += 1;
+  }
+  bt->kinds.clear();
+  bt->ev_used = 0;
+  bt->ev_error = false;
   return SSA_OK;
 }
 

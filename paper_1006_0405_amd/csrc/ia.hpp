@@ -120,26 +120,45 @@ __device__ __forceinline__ ci ci_conj(const ci &a) { return ci{a.rn, a.rh, a.ih,
 // Multiplication by a root of unity w, known as a point (c, s) with
 // |Re w - c| <= e and |Im w - s| <= e.  For x in [x], y in [y]:
 //   Re(w z) = c x - s y + (dc x - ds y),  |dc x - ds y| <= e (|x|max + |y|max)
-//   Im(w z) = s x + c y + (ds x + dc y),  same bound,
-// and for a point factor c the interval c[x] is [c x.lo, c x.hi] (c >= 0) or
-// [c x.hi, c x.lo] (c < 0).  Each bound is then one fused chain rounded up.
-// This encloses the paper's rectangular product [w][z] (section 2.5) with the
-// twiddle's rounding error folded into a common radius term.
+//   Im(w z) = s x + c y + (ds x + dc y),  same bound.
+// A point factor is split by sign, c = c+ - c- with c+ = max(c, 0) and
+// c- = max(-c, 0) (one of them is 0), so that without any branch or select
+//   hi(c [x])  = c+ x.hi + c- (-x.lo)   and   -lo(c [x]) = c+ (-x.lo) + c- x.hi,
+// and every bound is one fused chain rounded up.  This encloses the paper's
+// rectangular product [w][z] (section 2.5) with the twiddle's rounding error
+// folded into a common radius term.
 __device__ __forceinline__ ci ci_twiddle(const ci &z, double c, double s, double e) {
-  const double ac = dabs(c), as = dabs(s);
-  const bool cp = sign_clear(c), sp = sign_clear(s);
+  const double cp = dmax(c, 0.0), cn = dmax(-c, 0.0);
+  const double sp = dmax(s, 0.0), sn = dmax(-s, 0.0);
   const double mx = dmax(z.rn, z.rh), my = dmax(z.in, z.ih);
   const double E = ru_mul(e, ru_add(mx, my));
-  const double xh_c = cp ? z.rh : z.rn, xn_c = cp ? z.rn : z.rh;
-  const double yh_c = cp ? z.ih : z.in, yn_c = cp ? z.in : z.ih;
-  const double xh_s = sp ? z.rh : z.rn, xn_s = sp ? z.rn : z.rh;
-  const double yh_s = sp ? z.ih : z.in, yn_s = sp ? z.in : z.ih;
   ci r;
-  r.rh = ru_fma(ac, xh_c, ru_fma(as, yn_s, E));  // c x - s y, upper
-  r.rn = ru_fma(ac, xn_c, ru_fma(as, yh_s, E));  // -(c x - s y), upper
-  r.ih = ru_fma(as, xh_s, ru_fma(ac, yh_c, E));  // s x + c y, upper
-  r.in = ru_fma(as, xn_s, ru_fma(ac, yn_c, E));  // -(s x + c y), upper
+  // Re = c x - s y:  hi = hi(c x) + (-lo(s y)),  -lo = -lo(c x) + hi(s y)
+  r.rh = ru_fma(cp, z.rh, ru_fma(cn, z.rn, ru_fma(sp, z.in, ru_fma(sn, z.ih, E))));
+  r.rn = ru_fma(cp, z.rn, ru_fma(cn, z.rh, ru_fma(sp, z.ih, ru_fma(sn, z.in, E))));
+  // Im = s x + c y:  hi = hi(s x) + hi(c y),  -lo = -lo(s x) + (-lo(c y))
+  r.ih = ru_fma(sp, z.rh, ru_fma(sn, z.rn, ru_fma(cp, z.ih, ru_fma(cn, z.in, E))));
+  r.in = ru_fma(sp, z.rn, ru_fma(sn, z.rh, ru_fma(cp, z.in, ru_fma(cn, z.ih, E))));
   return r;
+}
+
+// The product of two stored roots w1 = (c1, s1), w2 = (c2, s2) (each within e
+// of the true root componentwise) as a point (c, s) with its own bound:
+// the exact product of the stored points lies in [-re_n, re_h] x [-im_n, im_h]
+// (bounds rounded up), and the true roots' product differs from it by at most
+// e (|c1| + |s1| + |c2| + |s2|) + 2 e^2 per component.
+struct twpoint {
+  double c, s, e;
+};
+__device__ __forceinline__ twpoint tw_product(double2 w1, double2 w2, double e) {
+  const double re_h = ru_fma(w1.x, w2.x, ru_nmul(w1.y, w2.y));
+  const double re_n = ru_fma(-w1.x, w2.x, ru_mul(w1.y, w2.y));
+  const double im_h = ru_fma(w1.x, w2.y, ru_mul(w1.y, w2.x));
+  const double im_n = ru_fma(-w1.x, w2.y, ru_nmul(w1.y, w2.x));
+  const double l1 = ru_add(ru_add(dabs(w1.x), dabs(w1.y)), ru_add(dabs(w2.x), dabs(w2.y)));
+  const double E2 = ru_fma(e, l1, ru_mul(ru_add(e, e), e));
+  const double ec = ru_add(ru_add(re_h, re_n), E2), es = ru_add(ru_add(im_h, im_n), E2);
+  return twpoint{re_h, im_h, dmax(ec, es)};
 }
 
 // Real interval product (paper section 2.5, four end-point products): with

@@ -38,10 +38,13 @@ struct task {
 
 enum { CERT_ONE_INTEGER = 0, CERT_HALF_INTEGER = 1 };
 
-// Tile of the carry scan: threads x positions per thread.
+// Tile of the carry scan: 4 wavefronts x 16 chunks of 64 positions.
 static constexpr int CARRY_THREADS = 256;
-static constexpr int CARRY_PER_THREAD = 16;
-static constexpr int CARRY_TILE = CARRY_THREADS * CARRY_PER_THREAD;
+static constexpr int CARRY_CHUNKS = 16;
+static constexpr int CARRY_TILE = CARRY_THREADS * CARRY_CHUNKS;
+// Tile status words sit one 128-byte line apart, so that spinning readers of
+// one tile do not contend with the publication of its neighbours.
+static constexpr uint32_t TILE_WORD_STRIDE = 32;
 
 // Largest transform done by one workgroup holding everything in LDS.
 static constexpr int SMALL_MAX_LOG = 12;
@@ -51,7 +54,8 @@ struct launch_cfg {
   int log_n1;  // column transform length (multi-pass)
   int log_n2;  // row transform length
   int cols;    // columns per workgroup in the column passes
-  int rows;    // rows per workgroup in the row pass
+  int rows;    // rows (row pairs when packed) per workgroup in the row pass
+  int pack;    // 1: one complex transform of a + i b; 0: one transform per operand
 };
 
 struct twtab_host {
@@ -60,16 +64,34 @@ struct twtab_host {
   double e;
 };
 
+// Optional timing: mark(ctx, kind, 0) right before and mark(ctx, kind, 1) right
+// after each kernel launch, on the launch stream.
+enum {
+  KIND_SMALL = 0,
+  KIND_COL_FWD = 1,
+  KIND_ROW = 2,
+  KIND_COL_INV = 3,
+  KIND_CARRY = 4,
+  KIND_STATUS = 5,
+  KIND_COUNT = 6
+};
+struct timing_hook {
+  void (*mark)(void *ctx, int kind, int phase);
+  void *ctx;
+};
+
 // dbg (nullable): N x 4 doubles {re_lo, re_hi, im_lo, im_hi} of the final
 // enclosures of task 0, written before certification.
 hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bits, int cert_mode,
-                        const twtab_host &tw, double *dbg, hipStream_t s);
+                        int pack, const twtab_host &tw, double *dbg, hipStream_t s,
+                        const timing_hook *hk = nullptr);
 hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const launch_cfg &cfg,
                             int digit_bits, int cert_mode, const twtab_host &tw, double *dbg,
-                            hipStream_t s);
+                            hipStream_t s, const timing_hook *hk = nullptr);
 hipError_t launch_carry(const task *d_tasks, int ntasks, uint32_t max_tiles, int digit_bits,
-                        hipStream_t s);
-hipError_t launch_status(const task *d_tasks, int ntasks, int *d_status, hipStream_t s);
+                        hipStream_t s, const timing_hook *hk = nullptr);
+hipError_t launch_status(const task *d_tasks, int ntasks, int *d_status, hipStream_t s,
+                         const timing_hook *hk = nullptr);
 hipError_t launch_directed_probe(int op, const double *a, const double *b, const double *c,
                                  double *out, size_t n, hipStream_t s);
 

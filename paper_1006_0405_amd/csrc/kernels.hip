@@ -140,37 +140,42 @@ __device__ __forceinline__ uint32_t s_at(F C, long long p) {
   return s;
 }
 
-// Tile of CH positions per thread.  `tile_cin(G, P)` is called by thread 0
-// with the tile's aggregate (carry-out for carry-in 0, all-propagate) and
-// returns the tile's carry-in.
-template <int CH, class F, class TC>
+// One tile of positions [p0, p0 + waves * CHUNKS * 64).  Wave w owns CHUNKS
+// consecutive chunks of 64 positions, one position per lane, so every load and
+// store is lane-contiguous.  Per chunk the (generate, propagate) masks come
+// from two ballots; a chunk's carry-out for carry-in c is G | (P & c) with
+// G = carry out of x + g and P = "all lanes propagate".  `tile_cin(G, P)` is
+// called by thread 0 with the tile's aggregate and returns the tile's carry-in.
+template <int CHUNKS, class F, class TC>
 __device__ __forceinline__ void carry_block(F C, long long p0, uint32_t nout, uint8_t *out,
                                             bool zero, TC tile_cin, uint32_t *sh_waves) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
-  const long long q0 = p0 + static_cast<long long>(tid) * CH;
-  uint32_t u[CH];
-  uint32_t sprev = s_at(C, q0 - 1);
+  const long long wbase = p0 + static_cast<long long>(wave) * (CHUNKS * 64);
+  uint32_t u[CHUNKS];
+  unsigned long long gm[CHUNKS], pm[CHUNKS];
+  uint32_t s_last = s_at(C, wbase - 1);  // s at the position before this wave's first
 #pragma unroll
-  for (int k = 0; k < CH; ++k) {
-    const uint32_t s = s_at(C, q0 + k);
-    u[k] = (s & 255u) + (sprev >> 8);
-    sprev = s;
+  for (int k = 0; k < CHUNKS; ++k) {
+    const long long p = wbase + k * 64 + lane;
+    const uint32_t s = s_at(C, p);
+    uint32_t sp = __shfl_up(s, 1);
+    if (lane == 0) sp = s_last;
+    s_last = __shfl(s, 63);
+    u[k] = (s & 255u) + (sp >> 8);
+    gm[k] = __ballot(u[k] >= 256u);
+    pm[k] = __ballot(u[k] == 255u);
   }
-  // thread aggregate
-  uint32_t G = 0, P = 1;
+  uint32_t WG = 0, WP = 1;
 #pragma unroll
-  for (int k = 0; k < CH; ++k) {
-    const uint32_t g = u[k] >= 256u, pr = u[k] == 255u;
-    G = g | (pr & G);
-    P = P & pr;
+  for (int k = 0; k < CHUNKS; ++k) {
+    const unsigned long long x = gm[k] | pm[k];
+    const uint32_t cg = (x + gm[k]) < x ? 1u : 0u;
+    const uint32_t cp = pm[k] == ~0ull ? 1u : 0u;
+    WG = cg | (cp & WG);
+    WP &= cp;
   }
-  const unsigned long long gm = __ballot(G != 0), pm = __ballot(P != 0);
-  const unsigned long long x = gm | pm;
-  const unsigned long long s0 = x + gm;
-  const uint32_t wG = s0 < x ? 1u : 0u;  // overflow: carry out of lane 63
-  const uint32_t wP = (pm == ~0ull) ? 1u : 0u;
-  if (lane == 0) sh_waves[wave] = (wG << 1) | wP;
+  if (lane == 0) sh_waves[wave] = (WG << 1) | WP;
   __syncthreads();
   if (tid == 0) {
     uint32_t TG = 0, TP = 1;
@@ -182,21 +187,34 @@ __device__ __forceinline__ void carry_block(F C, long long p0, uint32_t nout, ui
     uint32_t cin = zero ? 0u : tile_cin(TG, TP);
     for (int w = 0; w < nwaves; ++w) {
       const uint32_t a = sh_waves[w];
-      sh_waves[w] = (sh_waves[w] & 3u) | (cin << 2);
+      sh_waves[w] = (a & 3u) | (cin << 2);
       cin = ((a >> 1) & 1u) | ((a & 1u) & cin);
     }
   }
   __syncthreads();
-  const unsigned long long cw = (sh_waves[wave] >> 2) & 1u;
-  const unsigned long long carries = (x + gm + cw) ^ x ^ gm;
-  uint32_t cy = static_cast<uint32_t>((carries >> lane) & 1ull);
+  uint32_t cin = (sh_waves[wave] >> 2) & 1u;
 #pragma unroll
-  for (int k = 0; k < CH; ++k) {
-    const uint32_t v = u[k] + cy;
-    cy = v >> 8;
-    const long long p = q0 + k;
-    if (p >= 0 && p < static_cast<long long>(nout)) out[p] = zero ? 0 : static_cast<uint8_t>(v);
+  for (int k = 0; k < CHUNKS; ++k) {
+    const unsigned long long x = gm[k] | pm[k];
+    const unsigned long long carries = (x + gm[k] + cin) ^ x ^ gm[k];
+    const uint32_t cy = static_cast<uint32_t>((carries >> lane) & 1ull);
+    const long long p = wbase + k * 64 + lane;
+    if (p < static_cast<long long>(nout)) out[p] = zero ? 0 : static_cast<uint8_t>(u[k] + cy);
+    const uint32_t cg = (x + gm[k]) < x ? 1u : 0u;
+    const uint32_t cp = pm[k] == ~0ull ? 1u : 0u;
+    cin = cg | (cp & cin);
   }
+}
+
+// Both operands' transforms from one transform of z = a + i b (a, b real):
+// A_k = (Z_k + conj Z_{-k}) / 2 and B_k = (Z_k - conj Z_{-k}) / (2i); the
+// returned value encloses C_k = A_k B_k.  W = conj(Z_{-k}).  Conjugation,
+// multiplication by -i and by 1/2 are exact, so this is as rigorous as the
+// interval sum, difference and product it uses.
+__device__ __forceinline__ ci separated_product(const ci &Z, const ci &W) {
+  const ci A = ci_scale(ci_add(Z, W), 0.5);
+  const ci B = ci_scale(ci_mul_negi(ci_sub(Z, W)), 0.5);
+  return ci_mul(A, B);
 }
 
 // ---------------------------------------------------------------------------
@@ -204,7 +222,7 @@ __device__ __forceinline__ void carry_block(F C, long long p0, uint32_t nout, ui
 // 2^8 <= N <= 2^12.  LDS: N complex intervals (reused for the coefficients).
 
 __global__ __launch_bounds__(1024) void k_small(const task *tasks, int log_n, int bits, int mode,
-                                                twtab T, double *dbg) {
+                                                int pack, twtab T, double *dbg) {
   extern __shared__ ci lds[];
   __shared__ cert_shared sh;
   __shared__ uint32_t sh_waves[16];
@@ -215,17 +233,40 @@ __global__ __launch_bounds__(1024) void k_small(const task *tasks, int log_n, in
   const int j = threadIdx.x;
   if (j == 0) sh = cert_shared{0ull, 0ull, 0u, 0u};
 
-  ci va[4], vb[4];
+  ci va[4];
+  if (pack) {  // one transform of z = a + i b, then separation
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const uint32_t i = j + r * Q;
-    va[r] = ci_thin_real(static_cast<double>(digit(tk.a, tk.nda, i, bits)));
-    vb[r] = ci_thin_real(static_cast<double>(digit(tk.b, tk.ndb, i, bits)));
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t i = j + r * Q;
+      const double da = static_cast<double>(digit(tk.a, tk.nda, i, bits));
+      const double db = static_cast<double>(digit(tk.b, tk.ndb, i, bits));
+      va[r] = ci{-da, da, -db, db};
+    }
+    fft_group(va, j, log_n, lds, 1, T);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) lds_put(lds, j + r * Q, va[r]);
+    __syncthreads();
+    const uint32_t mask = (1u << log_n) - 1u;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t k = j + r * Q;
+      const ci W = ci_conj(lds_get(lds, (0u - k) & mask));
+      va[r] = ci_conj(separated_product(va[r], W));
+    }
+  } else {  // one transform per operand, pointwise product
+    ci vb[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t i = j + r * Q;
+      va[r] = ci_thin_real(static_cast<double>(digit(tk.a, tk.nda, i, bits)));
+      vb[r] = ci_thin_real(static_cast<double>(digit(tk.b, tk.ndb, i, bits)));
+    }
+    fft_group(va, j, log_n, lds, 1, T);
+    fft_group(vb, j, log_n, lds, 1, T);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) va[r] = ci_conj(ci_mul(va[r], vb[r]));
   }
-  fft_group(va, j, log_n, lds, 1, T);
-  fft_group(vb, j, log_n, lds, 1, T);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) va[r] = ci_conj(ci_mul(va[r], vb[r]));
   fft_group(va, j, log_n, lds, 1, T);
   const double scale = ldexp(1.0, -log_n);
   cert_acc acc{0.0, 0u, 0u, 0u};
@@ -275,16 +316,24 @@ __global__ __launch_bounds__(1024) void k_small(const task *tasks, int log_n, in
 // ---------------------------------------------------------------------------
 // Multi-pass kernels.
 
-// Twiddle omega_N^t for t = (a * b) mod N, from the table of omega_Ntab.
-__device__ __forceinline__ uint32_t tw_index(uint32_t a, uint32_t b, int log_n, int log_ntab) {
+// Inter-pass twiddle omega_N^t, t = (a * b) mod N, as the product of two table
+// entries omega_N^{t_hi} omega_N^{t_lo} (t_hi a multiple of 2^h, t_lo < 2^h):
+// the two factors come from 2^(log_n - h) and 2^h entries of the table, which
+// stay cache-resident, instead of one scattered read over all N entries.
+__device__ __forceinline__ ci apply_pass_tw(const ci &v, const twtab &T, uint32_t a, uint32_t b,
+                                            int log_n) {
   const uint32_t t = (a * b) & ((1u << log_n) - 1u);
-  return t << (log_ntab - log_n);
+  const int h = (log_n + 1) >> 1;
+  const int sh = T.log_ntab - log_n;
+  const uint32_t thi = (t >> h) << h, tlo = t & ((1u << h) - 1u);
+  const twpoint w = tw_product(T.tab[thi << sh], T.tab[tlo << sh], T.e);
+  return ci_twiddle(v, w.c, w.s, w.e);
 }
 
 // Columns: thread (c, j) with c = tid % C fastest, so that the C columns of a
 // workgroup are adjacent in memory.  grid = (N2 / C, 2 operands, tasks).
 __global__ __launch_bounds__(1024) void k_col_fwd(const task *tasks, int log_n1, int log_n2,
-                                                  int C, int bits, twtab T) {
+                                                  int C, int bits, int pack, twtab T) {
   extern __shared__ ci lds[];
   const uint32_t z = enter_round_up();
   const task tk = after_mode(tasks, z)[blockIdx.z];
@@ -304,7 +353,7 @@ __global__ __launch_bounds__(1024) void k_col_fwd(const task *tasks, int log_n1,
       tk.st->carry_err = 0u;
       tk.st->ticket = 0u;
     }
-    for (uint32_t t = threadIdx.x; t < tk.ntiles; t += blockDim.x) tk.tiles[t] = 0u;
+    for (uint32_t t = threadIdx.x; t < tk.ntiles; t += blockDim.x) tk.tiles[t * TILE_WORD_STRIDE] = 0u;
   }
   const uint8_t *p = opb ? tk.b : tk.a;
   const uint32_t nd = opb ? tk.ndb : tk.nda;
@@ -312,20 +361,27 @@ __global__ __launch_bounds__(1024) void k_col_fwd(const task *tasks, int log_n1,
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const uint32_t n1 = j + r * Q;
-    v[r] = ci_thin_real(static_cast<double>(digit(p, nd, (n1 << log_n2) + n2, bits)));
+    const uint32_t i = (n1 << log_n2) + n2;
+    if (pack) {  // z = a + i b: both real operands in one complex transform
+      const double da = static_cast<double>(digit(tk.a, tk.nda, i, bits));
+      const double db = static_cast<double>(digit(tk.b, tk.ndb, i, bits));
+      v[r] = ci{-da, da, -db, db};
+    } else {
+      v[r] = ci_thin_real(static_cast<double>(digit(p, nd, i, bits)));
+    }
   }
   fft_group(v, j, log_n1, lds + c, C, T);
   ci *Y = opb ? tk.yb : tk.ya;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const uint32_t k1 = j + q * Q;
-    const ci w = apply_tw(v[q], T, tw_index(n2, k1, log_n, T.log_ntab));
+    const ci w = apply_pass_tw(v[q], T, n2, k1, log_n);
     gst(Y, (static_cast<size_t>(k1) << log_n2) + n2, w);
   }
 }
 
 // Rows: R rows k1 per workgroup, N2/4 threads per row.  grid = (N1 / R, tasks).
-__global__ __launch_bounds__(1024) void k_row(const task *tasks, int log_n1, int log_n2, int R,
+__global__ __launch_bounds__(512) void k_row(const task *tasks, int log_n1, int log_n2, int R,
                                               twtab T) {
   extern __shared__ ci lds[];
   const uint32_t z = enter_round_up();
@@ -351,8 +407,86 @@ __global__ __launch_bounds__(1024) void k_row(const task *tasks, int log_n1, int
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const uint32_t n2 = j + q * Q;
-    const ci w = ci_conj(apply_tw(va[q], T, tw_index(n2, k1, log_n, T.log_ntab)));
+    const ci w = ci_conj(apply_pass_tw(va[q], T, n2, k1, log_n));
     gst(tk.ya, row + n2, w);
+  }
+}
+
+// Row pairs for the packed transform: group g of N2/4 threads handles the
+// rows k1 and N1 - k1 (pair p >= 1, k1 = p) or the two self-paired rows 0 and
+// N1/2 (p = 0).  Index k = k1 + N1 k2 has -k = (N1 - k1) + N1 (N2 - 1 - k2) for
+// k1 > 0 and -k = N1 ((N2 - k2) mod N2) for k1 = 0, so the partner Z_{-k} of
+// every element of a pair lies in the same pair.  For a general pair only the
+// products of row k1 are formed; row N1 - k1 gets C_{-k} = conj(C_k), exact
+// because the convolution is real.  Per row: forward length-N2 DFT, the
+// separated pointwise product, the length-N2 DFT of the conjugate and the
+// conjugate inter-pass twiddle.  grid = (N1 / 2 / G, tasks).
+__global__ __launch_bounds__(512) void k_row_pair(const task *tasks, int log_n1, int log_n2,
+                                                  int G, twtab T) {
+  extern __shared__ ci lds[];
+  const uint32_t z = enter_round_up();
+  const task tk = after_mode(tasks, z)[blockIdx.y];
+  T.tab = after_mode(T.tab, z);
+  const int log_n = log_n1 + log_n2;
+  const uint32_t N1 = 1u << log_n1, N2 = 1u << log_n2;
+  const int Q = 1 << (log_n2 - 2);
+  const int g = threadIdx.x / Q, j = threadIdx.x % Q;
+  const uint32_t p = blockIdx.x * G + g;
+  const bool self = p == 0;  // rows 0 and N1/2, each its own partner
+  const uint32_t k1a = p, k1b = self ? N1 / 2 : N1 - p;
+  ci *L0 = lds + (static_cast<size_t>(g) << log_n2);
+  const size_t rowA = static_cast<size_t>(k1a) << log_n2, rowB = static_cast<size_t>(k1b) << log_n2;
+  ci va[4], vb[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    va[r] = gld(tk.ya, rowA + j + r * Q);
+    vb[r] = gld(tk.ya, rowB + j + r * Q);
+  }
+  fft_group(va, j, log_n2, L0, 1, T);
+  fft_group(vb, j, log_n2, L0, 1, T);
+  // round 1: the partners of row k1 (from row N1 - k1, or from row 0 itself)
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) lds_put(L0, j + r * Q, self ? va[r] : vb[r]);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t k2 = j + r * Q;
+    const uint32_t src = self ? ((N2 - k2) & (N2 - 1)) : (N2 - 1 - k2);
+    va[r] = separated_product(va[r], ci_conj(lds_get(L0, src)));
+  }
+  // round 2: row N1 - k1 from conj(C_k), or row N1/2 from its own partners
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t k2 = j + r * Q;
+    if (self)
+      lds_put(L0, k2, vb[r]);
+    else
+      lds_put(L0, N2 - 1 - k2, ci_conj(va[r]));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t k2 = j + r * Q;
+    vb[r] = self ? separated_product(vb[r], ci_conj(lds_get(L0, N2 - 1 - k2))) : lds_get(L0, k2);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    va[r] = ci_conj(va[r]);
+    vb[r] = ci_conj(vb[r]);
+  }
+  fft_group(va, j, log_n2, L0, 1, T);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t n2 = j + q * Q;
+    gst(tk.ya, rowA + n2, ci_conj(apply_pass_tw(va[q], T, n2, k1a, log_n)));
+  }
+  fft_group(vb, j, log_n2, L0, 1, T);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t n2 = j + q * Q;
+    gst(tk.ya, rowB + n2, ci_conj(apply_pass_tw(vb[q], T, n2, k1b, log_n)));
   }
 }
 
@@ -384,7 +518,8 @@ __global__ __launch_bounds__(1024) void k_col_inv(const task *tasks, int log_n1,
     const uint32_t i = (n1 << log_n2) + n2;
     const ci w = ci_scale(ci_conj(v[q]), scale);
     if (dbg != nullptr && blockIdx.y == 0) dbg_store(dbg, i, w);
-    tk.c[i] = certify(w, i, tk.L, mode, acc);
+    const unsigned long long cv = certify(w, i, tk.L, mode, acc);
+    if (i < tk.L) tk.c[i] = cv;
   }
   cert_reduce(sh, acc);
   __syncthreads();
@@ -397,7 +532,10 @@ __global__ __launch_bounds__(1024) void k_col_inv(const task *tasks, int log_n1,
 }
 
 // Decoupled look-back (Merrill & Garland): tile status word = flag << 2 | bits,
-// flag 1: aggregate (G << 1 | P), flag 2: inclusive carry-out.  Tile numbers
+// flag 1: aggregate (G << 1 | P), flag 2: inclusive carry-out.  The word holds
+// all the information a reader needs, so relaxed device-scope atomics suffice;
+// acquire/release at device scope would also write back or invalidate the
+// XCD's L2 on every poll.  Tile numbers
 // come from a ticket counter in start order, so every tile looked at belongs to
 // a workgroup that is already running and never waits itself before
 // publishing its aggregate: the wait always ends.  A generous spin limit turns
@@ -407,23 +545,24 @@ static constexpr uint32_t SPIN_LIMIT = 1u << 22;
 __device__ uint32_t lookback(uint32_t *tiles, uint32_t tile, uint32_t G, uint32_t P,
                              unsigned int *err) {
   if (tile == 0) {
-    __hip_atomic_store(&tiles[0], (2u << 2) | G, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&tiles[0], (2u << 2) | G, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return 0u;
   }
-  __hip_atomic_store(&tiles[tile], (1u << 2) | (G << 1) | P, __ATOMIC_RELEASE,
+  __hip_atomic_store(&tiles[tile * TILE_WORD_STRIDE], (1u << 2) | (G << 1) | P, __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
   uint32_t cin = 0u;
   int idx = static_cast<int>(tile) - 1;
   uint32_t spins = 0u;
   while (idx >= 0) {
-    const uint32_t w = __hip_atomic_load(&tiles[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t w =
+        __hip_atomic_load(&tiles[idx * TILE_WORD_STRIDE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t f = w >> 2;
     if (f == 0u) {
       if (++spins > SPIN_LIMIT) {
         atomicAdd(err, 1u);
         break;
       }
-      __builtin_amdgcn_s_sleep(1);
+      __builtin_amdgcn_s_sleep(4);
       continue;
     }
     if (f == 2u) {
@@ -440,38 +579,48 @@ __device__ uint32_t lookback(uint32_t *tiles, uint32_t tile, uint32_t G, uint32_
     }
     --idx;  // predecessor propagates: look further back
   }
-  __hip_atomic_store(&tiles[tile], (2u << 2) | (G | (P & cin)), __ATOMIC_RELEASE,
-                     __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&tiles[tile * TILE_WORD_STRIDE], (2u << 2) | (G | (P & cin)),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return cin;
 }
 
-// grid = (max tiles, tasks), CARRY_THREADS threads.
+// grid = (max tiles, tasks), CARRY_THREADS threads.  The tile's coefficients
+// (with 8 before it) are staged in LDS by coalesced loads first, so the six
+// overlapping reads per position hit LDS and each lane issues few global loads.
 __global__ __launch_bounds__(CARRY_THREADS) void k_carry(const task *tasks, int bits) {
   __shared__ uint32_t sh_waves[CARRY_THREADS / 64];
   __shared__ uint32_t sh_tile;
+  __shared__ uint32_t sh_failed;
+  __shared__ unsigned long long sC[CARRY_TILE + 8];
   const task tk = tasks[blockIdx.y];
   if (blockIdx.x >= tk.ntiles) return;
-  if (threadIdx.x == 0) sh_tile = atomicAdd(&tk.st->ticket, 1u);
+  if (threadIdx.x == 0) {
+    sh_tile = atomicAdd(&tk.st->ticket, 1u);
+    sh_failed = (tk.st->too_wide + tk.st->internal) != 0u ? 1u : 0u;
+  }
   __syncthreads();
   const uint32_t tile = sh_tile;
-  const bool failed = (__hip_atomic_load(&tk.st->too_wide, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
-                       __hip_atomic_load(&tk.st->internal, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0u;
+  const bool failed = sh_failed != 0u;
   const long long p0 = static_cast<long long>(tile) * CARRY_TILE;
+  const long long base = p0 - 8;
   const uint32_t nout = tk.na + tk.nb;
   const unsigned long long *c = tk.c;
   const long long L = tk.L;
-  auto tc = [&](uint32_t G, uint32_t P) { return lookback(tk.tiles, tile, G, P, &tk.st->carry_err); };
   if (bits == 8) {
-    auto C = [&](long long q) -> unsigned long long { return (q >= 0 && q < L) ? c[q] : 0ull; };
-    carry_block<CARRY_PER_THREAD>(C, p0, nout, tk.out, failed, tc, sh_waves);
+    for (int t = threadIdx.x; t < CARRY_TILE + 8; t += CARRY_THREADS) {
+      const long long q = base + t;
+      sC[t] = (q >= 0 && q < L) ? c[q] : 0ull;
+    }
   } else {
-    auto C = [&](long long q) -> unsigned long long {
-      if (q < 0) return 0ull;
-      const long long i0 = 2 * q, i1 = 2 * q + 1;
-      return (i0 < L ? c[i0] : 0ull) + 16ull * (i1 < L ? c[i1] : 0ull);
-    };
-    carry_block<CARRY_PER_THREAD>(C, p0, nout, tk.out, failed, tc, sh_waves);
+    for (int t = threadIdx.x; t < CARRY_TILE + 8; t += CARRY_THREADS) {
+      const long long q = base + t, i0 = 2 * q, i1 = 2 * q + 1;
+      sC[t] = q < 0 ? 0ull : (i0 < L ? c[i0] : 0ull) + 16ull * (i1 < L ? c[i1] : 0ull);
+    }
   }
+  __syncthreads();
+  auto C = [&](long long q) -> unsigned long long { return sC[q - base]; };
+  auto tc = [&](uint32_t G, uint32_t P) { return lookback(tk.tiles, tile, G, P, &tk.st->carry_err); };
+  carry_block<CARRY_CHUNKS>(C, p0, nout, tk.out, failed, tc, sh_waves);
 }
 
 // Final status per product: 0 ok, 1 too wide, 4 device error, 5 internal.
@@ -522,6 +671,7 @@ hipError_t set_kernel_attributes() {
   const void *ks[] = {reinterpret_cast<const void *>(&k_small),
                       reinterpret_cast<const void *>(&k_col_fwd),
                       reinterpret_cast<const void *>(&k_row),
+                      reinterpret_cast<const void *>(&k_row_pair),
                       reinterpret_cast<const void *>(&k_col_inv)};
   for (const void *k : ks) {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, MAX_DYN_LDS);
@@ -538,42 +688,64 @@ hipError_t launch_scatter_status(const int *slot_status, const int *order, int n
 
 static twtab to_dev(const twtab_host &t) { return twtab{t.tab, t.log_ntab, t.e}; }
 
+static inline void mark(const timing_hook *hk, int kind, int phase) {
+  if (hk != nullptr) hk->mark(hk->ctx, kind, phase);
+}
+
 hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bits, int cert_mode,
-                        const twtab_host &tw, double *dbg, hipStream_t s) {
+                        int pack, const twtab_host &tw, double *dbg, hipStream_t s,
+                        const timing_hook *hk) {
   const int threads = 1 << (log_n - 2);
   const size_t lds = sizeof(ci) << log_n;
+  mark(hk, KIND_SMALL, 0);
   hipLaunchKernelGGL(k_small, dim3(ntasks), dim3(threads), lds, s, d_tasks, log_n, digit_bits,
-                     cert_mode, to_dev(tw), dbg);
+                     cert_mode, pack, to_dev(tw), dbg);
+  mark(hk, KIND_SMALL, 1);
   return hipGetLastError();
 }
 
 hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const launch_cfg &cfg,
                             int digit_bits, int cert_mode, const twtab_host &tw, double *dbg,
-                            hipStream_t s) {
+                            hipStream_t s, const timing_hook *hk) {
   const int l1 = cfg.log_n1, l2 = cfg.log_n2;
   const uint32_t N1 = 1u << l1, N2 = 1u << l2;
   const twtab T = to_dev(tw);
   {
     const int threads = cfg.cols * static_cast<int>(N1 / 4);
     const size_t lds = sizeof(ci) * N1 * cfg.cols;
-    hipLaunchKernelGGL(k_col_fwd, dim3(N2 / cfg.cols, 2, ntasks), dim3(threads), lds, s, d_tasks,
-                       l1, l2, cfg.cols, digit_bits, T);
+    mark(hk, KIND_COL_FWD, 0);
+    hipLaunchKernelGGL(k_col_fwd, dim3(N2 / cfg.cols, cfg.pack ? 1 : 2, ntasks), dim3(threads), lds,
+                       s, d_tasks, l1, l2, cfg.cols, digit_bits, cfg.pack, T);
+    mark(hk, KIND_COL_FWD, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  {
+  if (cfg.pack) {
     const int threads = cfg.rows * static_cast<int>(N2 / 4);
     const size_t lds = sizeof(ci) * N2 * cfg.rows;
+    mark(hk, KIND_ROW, 0);
+    hipLaunchKernelGGL(k_row_pair, dim3(N1 / 2 / cfg.rows, ntasks), dim3(threads), lds, s, d_tasks,
+                       l1, l2, cfg.rows, T);
+    mark(hk, KIND_ROW, 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  } else {
+    const int threads = cfg.rows * static_cast<int>(N2 / 4);
+    const size_t lds = sizeof(ci) * N2 * cfg.rows;
+    mark(hk, KIND_ROW, 0);
     hipLaunchKernelGGL(k_row, dim3(N1 / cfg.rows, ntasks), dim3(threads), lds, s, d_tasks, l1, l2,
                        cfg.rows, T);
+    mark(hk, KIND_ROW, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   {
     const int threads = cfg.cols * static_cast<int>(N1 / 4);
     const size_t lds = sizeof(ci) * N1 * cfg.cols;
+    mark(hk, KIND_COL_INV, 0);
     hipLaunchKernelGGL(k_col_inv, dim3(N2 / cfg.cols, ntasks), dim3(threads), lds, s, d_tasks, l1,
                        l2, cfg.cols, cert_mode, T, dbg);
+    mark(hk, KIND_COL_INV, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -582,15 +754,20 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
 }
 
 hipError_t launch_carry(const task *d_tasks, int ntasks, uint32_t max_tiles, int digit_bits,
-                        hipStream_t s) {
+                        hipStream_t s, const timing_hook *hk) {
+  mark(hk, KIND_CARRY, 0);
   hipLaunchKernelGGL(k_carry, dim3(max_tiles, ntasks), dim3(CARRY_THREADS), 0, s, d_tasks,
                      digit_bits);
+  mark(hk, KIND_CARRY, 1);
   return hipGetLastError();
 }
 
-hipError_t launch_status(const task *d_tasks, int ntasks, int *d_status, hipStream_t s) {
+hipError_t launch_status(const task *d_tasks, int ntasks, int *d_status, hipStream_t s,
+                         const timing_hook *hk) {
+  mark(hk, KIND_STATUS, 0);
   hipLaunchKernelGGL(k_status, dim3((ntasks + 255) / 256), dim3(256), 0, s, d_tasks, ntasks,
                      d_status);
+  mark(hk, KIND_STATUS, 1);
   return hipGetLastError();
 }
 

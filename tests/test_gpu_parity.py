@@ -128,9 +128,10 @@ def test_tiny_products():
     plan.close()
 
 
+@pytest.mark.parametrize("separate", [False, True], ids=["packed", "separate"])
 @pytest.mark.parametrize("digit_bits", [8, 4])
-def test_small_path_ragged_sizes(digit_bits):
-    plan = binding.Plan(2048, 2048, digit_bits=digit_bits)
+def test_small_path_ragged_sizes(digit_bits, separate):
+    plan = binding.Plan(2048, 2048, digit_bits=digit_bits, separate_transforms=separate)
     sizes = [(1, 1), (1, 2), (2, 1), (3, 5), (17, 33), (64, 65), (127, 2), (128, 129), (200, 57),
              (255, 256), (511, 512), (1000, 1), (1023, 1025), (2048, 2048), (1500, 300)]
     for s, (na, nb) in enumerate(sizes):
@@ -164,12 +165,13 @@ def test_config1_product_vs_oracle_and_schoolbook():
     plan.close()
 
 
+@pytest.mark.parametrize("separate", [False, True], ids=["packed", "separate"])
 @pytest.mark.parametrize("na,nb,digit_bits", [(1, 1, 8), (300, 200, 8), (1024, 1024, 8),
                                               (2048, 2047, 8), (3000, 2500, 8), (5000, 9000, 8),
                                               (16000, 16384, 8), (700, 900, 4), (9000, 7000, 4)])
-def test_enclosures_contain_exact_coefficients(na, nb, digit_bits):
+def test_enclosures_contain_exact_coefficients(na, nb, digit_bits, separate):
     a, b = pair(na * 7 + nb, na, nb)
-    plan = binding.Plan(na, nb, digit_bits=digit_bits)
+    plan = binding.Plan(na, nb, digit_bits=digit_bits, separate_transforms=separate)
     st, out, enc = plan.debug_enclosures(a, b)
     enc = _np(enc)
     assert st == binding.SSA_OK
@@ -186,11 +188,12 @@ def test_enclosures_contain_exact_coefficients(na, nb, digit_bits):
     plan.close()
 
 
+@pytest.mark.parametrize("separate", [False, True], ids=["packed", "separate"])
 @pytest.mark.parametrize("na,nb", [(2049, 2048), (4096, 4096), (6000, 3000), (8192, 8192),
                                    (16384, 16384), (20000, 12000)])
-def test_multipass_products_vs_oracle(na, nb):
+def test_multipass_products_vs_oracle(na, nb, separate):
     a, b = pair(na + 3 * nb, na, nb)
-    plan = binding.Plan(na, nb)
+    plan = binding.Plan(na, nb, separate_transforms=separate)
     _check_product(plan, a, b)
     plan.close()
 
@@ -204,9 +207,10 @@ def test_all_ff_multipass(n, m):
     plan.close()
 
 
-def test_config2_random_and_all_ff():
+@pytest.mark.parametrize("separate", [False, True], ids=["packed", "separate"])
+def test_config2_random_and_all_ff(separate):
     n = 75000
-    plan = binding.Plan(n, n)
+    plan = binding.Plan(n, n, separate_transforms=separate)
     a, b = pair(2, n)
     st, out = plan.mul(a, b)
     out = _np(out)
@@ -215,7 +219,8 @@ def test_config2_random_and_all_ff():
     assert np.array_equal(out, int_product(a, b))
     ost, oout, orad, _ = oracle.mul(a, b)
     assert ost == oracle.ST_OK and np.array_equal(out, oout)
-    print("config2 random: GPU max radius %.4f, oracle %.4f" % (rad, orad))
+    print("config2 random (%s): GPU max radius %.4f, oracle %.4f"
+          % ("separate" if separate else "packed", rad, orad))
     f = all_ff(n)
     st, out = plan.mul(f, f)
     assert st == binding.SSA_OK
@@ -224,9 +229,10 @@ def test_config2_random_and_all_ff():
     plan.close()
 
 
-def test_config5_base16_random_and_all_ff():
+@pytest.mark.parametrize("separate", [False, True], ids=["packed", "separate"])
+def test_config5_base16_random_and_all_ff(separate):
     n = 1_000_000
-    plan = binding.Plan(n, n, digit_bits=4)
+    plan = binding.Plan(n, n, digit_bits=4, separate_transforms=separate)
     a, b = pair(5, n)
     st, out = plan.mul(a, b)
     assert st == binding.SSA_OK, binding.STATUS_NAMES.get(st, st)
