@@ -32,15 +32,28 @@ __device__ __forceinline__ ci lds_get(const ci *lds, int idx) {
   const double2 a = p[0], b = p[1];
   return ci{a.x, a.y, b.x, b.y};
 }
+// Global-memory accesses through address-space-1 pointers, so that the
+// compiler emits global (not flat) loads and stores for pointers that came out
+// of a descriptor in memory.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const d2v *gcd2;
+typedef __attribute__((address_space(1))) d2v *gd2;
 __device__ __forceinline__ ci gld(const ci *g, size_t idx) {
-  const double2 *p = reinterpret_cast<const double2 *>(g + idx);
-  const double2 a = p[0], b = p[1];
+  const gcd2 p = reinterpret_cast<gcd2>(reinterpret_cast<uintptr_t>(g + idx));
+  const d2v a = p[0], b = p[1];
   return ci{a.x, a.y, b.x, b.y};
 }
 __device__ __forceinline__ void gst(ci *g, size_t idx, const ci &v) {
-  double2 *p = reinterpret_cast<double2 *>(g + idx);
-  p[0] = make_double2(v.rn, v.rh);
-  p[1] = make_double2(v.in, v.ih);
+  const gd2 p = reinterpret_cast<gd2>(reinterpret_cast<uintptr_t>(g + idx));
+  p[0] = d2v{v.rn, v.rh};
+  p[1] = d2v{v.in, v.ih};
+}
+
+template <class T> __device__ __forceinline__ T gload(const T *p) {
+  return *reinterpret_cast<__attribute__((address_space(1))) const T *>(reinterpret_cast<uintptr_t>(p));
+}
+template <class T> __device__ __forceinline__ void gstore(T *p, T v) {
+  *reinterpret_cast<__attribute__((address_space(1))) T *>(reinterpret_cast<uintptr_t>(p)) = v;
 }
 
 // Length-4 DFT with omega_4 = +i:  y0 = a + c, y2 = a - c, y1 = b + i d,

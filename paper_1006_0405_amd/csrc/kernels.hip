@@ -31,8 +31,8 @@ namespace ssa {
 
 __device__ __forceinline__ uint32_t digit(const uint8_t *p, uint32_t nd, uint32_t i, int bits) {
   if (i >= nd) return 0u;
-  if (bits == 8) return p[i];
-  const uint32_t byte = p[i >> 1];
+  if (bits == 8) return gload(p + i);
+  const uint32_t byte = gload(p + (i >> 1));
   return (i & 1u) ? (byte >> 4) : (byte & 15u);
 }
 
@@ -199,7 +199,8 @@ __device__ __forceinline__ void carry_block(F C, long long p0, uint32_t nout, ui
     const unsigned long long carries = (x + gm[k] + cin) ^ x ^ gm[k];
     const uint32_t cy = static_cast<uint32_t>((carries >> lane) & 1ull);
     const long long p = wbase + k * 64 + lane;
-    if (p < static_cast<long long>(nout)) out[p] = zero ? 0 : static_cast<uint8_t>(u[k] + cy);
+    if (p < static_cast<long long>(nout))
+      gstore(out + p, zero ? static_cast<uint8_t>(0) : static_cast<uint8_t>(u[k] + cy));
     const uint32_t cg = (x + gm[k]) < x ? 1u : 0u;
     const uint32_t cp = pm[k] == ~0ull ? 1u : 0u;
     cin = cg | (cp & cin);
@@ -519,7 +520,7 @@ __global__ __launch_bounds__(1024) void k_col_inv(const task *tasks, int log_n1,
     const ci w = ci_scale(ci_conj(v[q]), scale);
     if (dbg != nullptr && blockIdx.y == 0) dbg_store(dbg, i, w);
     const unsigned long long cv = certify(w, i, tk.L, mode, acc);
-    if (i < tk.L) tk.c[i] = cv;
+    if (i < tk.L) gstore(tk.c + i, cv);
   }
   cert_reduce(sh, acc);
   __syncthreads();
@@ -609,12 +610,12 @@ __global__ __launch_bounds__(CARRY_THREADS) void k_carry(const task *tasks, int 
   if (bits == 8) {
     for (int t = threadIdx.x; t < CARRY_TILE + 8; t += CARRY_THREADS) {
       const long long q = base + t;
-      sC[t] = (q >= 0 && q < L) ? c[q] : 0ull;
+      sC[t] = (q >= 0 && q < L) ? gload(c + q) : 0ull;
     }
   } else {
     for (int t = threadIdx.x; t < CARRY_TILE + 8; t += CARRY_THREADS) {
       const long long q = base + t, i0 = 2 * q, i1 = 2 * q + 1;
-      sC[t] = q < 0 ? 0ull : (i0 < L ? c[i0] : 0ull) + 16ull * (i1 < L ? c[i1] : 0ull);
+      sC[t] = q < 0 ? 0ull : (i0 < L ? gload(c + i0) : 0ull) + 16ull * (i1 < L ? gload(c + i1) : 0ull);
     }
   }
   __syncthreads();
