@@ -79,7 +79,7 @@ typedef struct ssa_batch ssa_batch;
 
 /* Transform length N = 2^k with k = ceil(log2(L)), L = digits(a) + digits(b) - 1
  * (section 2.3, fast convolution box, generalised to unequal lengths); products
- * with L <= 128 are padded to N = 256 (zero padding does not change them). */
+ * with L <= 256 are padded to N = 512 (zero padding does not change them). */
 size_t ssa_fft_size(size_t na, size_t nb, int digit_bits);
 
 /* Create a plan for products with na <= max_na, nb <= max_nb bytes.  Allocates

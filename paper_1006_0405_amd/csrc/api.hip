@@ -32,18 +32,21 @@ int log_n_for(uint64_t L) { return std::max(ceil_log2(L), SMALL_MIN_LOG); }
 
 uint64_t digits(size_t n, int bits) { return bits == 4 ? 2 * uint64_t(n) : uint64_t(n); }
 
-// Default launch shape of the three-pass path for N = 2^log_n.
+// Default launch shape of the three-pass path for N = 2^log_n (8 elements per
+// thread): C adjacent columns per column-pass workgroup (256 threads, 512 for
+// N1 = 2^11), and G rows (or row pairs) per row-pass workgroup.
 launch_cfg default_cfg(int log_n, int pack) {
   launch_cfg c;
   c.log_n1 = log_n / 2;
   c.log_n2 = log_n - c.log_n1;
   const int N1 = 1 << c.log_n1, N2 = 1 << c.log_n2;
-  c.cols = std::max(2, std::min(16, 2048 / N1));
+  c.cols = std::max(2, std::min(32, 2048 / N1));
   c.pack = pack;
-  if (pack)  // row pairs: one LDS row per pair, at most 512 threads
-    c.rows = std::max(1, std::min(N1 / 2, 1024 / N2));
+  const int t = N2 / 8;  // threads per row
+  if (pack)
+    c.rows = std::max(1, std::min(N1 / 2, 128 / t));
   else
-    c.rows = std::max(1, std::min(8, 1024 / N2));
+    c.rows = std::max(1, std::min(N1, 256 / t));
   return c;
 }
 

@@ -1,21 +1,6 @@
-// Interval DFT of length M = 2^m computed cooperatively by the M/4 threads of a
-// thread group, data in registers, exchanges through LDS.
-//
-// The transform is the DFT of the paper (section 2.2) with omega = e^{+2 pi i/M}.
-// Instead of the recursive radix-2 Cooley-Tukey box it uses the Stockham
-// (self-sorting) formulation of the same factorisation with radix 4 (and one
-// radix-2 stage when m is odd): input and output are in natural order, every
-// stage reads the group's elements with unit stride (coalesced from global
-// memory on the first stage, conflict-light in LDS afterwards), and the radix-4
-// kernel's inner twiddles are +-1 and +-i, which are exact in rectangular
-// interval arithmetic (no wrapping), so only one twiddle multiplication per
-// element and per two levels is interval-inexact.
-//
-// Stage s with radix R and Ns = product of the earlier radices: thread j takes
-// v_r = x[j + r M/R], multiplies v_r by omega_{R Ns}^{r k} (k = j mod Ns), applies
-// the length-R DFT and writes result q to y[(j - k) R + k + q Ns].  After the
-// last stage (R Ns = M) result q of thread j is X[j + q M/4], already in the
-// thread's own registers.
+// Building blocks of the interval DFT: global and LDS element access, the
+// length-4 DFT (inner twiddles +-1, +-i are exact permutations in rectangular
+// interval arithmetic, so they cause no wrapping) and the twiddle table.
 #pragma once
 #include "ia.hpp"
 
@@ -79,50 +64,6 @@ struct twtab {
 __device__ __forceinline__ ci apply_tw(const ci &v, const twtab &T, uint32_t t) {
   const double2 w = T.tab[t];
   return ci_twiddle(v, w.x, w.y, T.e);
-}
-
-// Forward interval DFT of the group's M elements.  `lds` points at element 0
-// of this group's exchange buffer; element i lives at lds[i * is].  All threads
-// of the workgroup must call this with the same M (it contains barriers).
-__device__ __forceinline__ void fft_group(ci v[4], int j, int logM, ci *lds, int is,
-                                          const twtab &T) {
-  const int M = 1 << logM;
-  const int Q = M >> 2;
-  int logNs = 0;
-  if (logM & 1) {
-    // Radix-2 stage with Ns = 1 (no twiddles).  This thread acts for the two
-    // radix-2 positions j (pair v0, v2) and j + M/4 (pair v1, v3).
-    const ci a0 = ci_add(v[0], v[2]), a1 = ci_sub(v[0], v[2]);
-    const ci b0 = ci_add(v[1], v[3]), b1 = ci_sub(v[1], v[3]);
-    __syncthreads();
-    lds_put(lds, (2 * j) * is, a0);
-    lds_put(lds, (2 * j + 1) * is, a1);
-    lds_put(lds, (2 * j + 2 * Q) * is, b0);
-    lds_put(lds, (2 * j + 2 * Q + 1) * is, b1);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] = lds_get(lds, (j + r * Q) * is);
-    logNs = 1;
-  }
-  for (;;) {
-    const int Ns = 1 << logNs;
-    const int k = j & (Ns - 1);
-    if (logNs > 0) {
-      const int sh = T.log_ntab - (logNs + 2);
-#pragma unroll
-      for (int r = 1; r < 4; ++r) v[r] = apply_tw(v[r], T, static_cast<uint32_t>(r * k) << sh);
-    }
-    radix4(v);
-    if (logNs + 2 == logM) break;  // last stage: X[j + q M/4] = v[q]
-    const int base = ((j - k) << 2) + k;
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) lds_put(lds, (base + q * Ns) * is, v[q]);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] = lds_get(lds, (j + r * Q) * is);
-    logNs += 2;
-  }
 }
 
 }  // namespace ssa

@@ -1,0 +1,163 @@
+// Interval DFT of length M = 2^m (m >= 3) computed cooperatively by the M/8
+// threads of a thread group, 8 elements per thread in registers, exchanges
+// through LDS.
+//
+// The transform is the DFT of the paper (section 2.2) with omega = e^{+2 pi i/M}.
+// It uses the Stockham (self-sorting) form of the Cooley-Tukey factorisation:
+// one radix-2 or radix-4 stage when m is not a multiple of 3, then radix-8
+// stages.  Stage s with radix R and Ns = product of the earlier radices: thread
+// j takes v_r = x[j + r M/R], multiplies v_r by omega_{R Ns}^{r k} (k = j mod Ns),
+// applies the length-R DFT and writes result q to y[(j - k) R + k + q Ns].  After
+// the last stage (R Ns = M) result q of thread j is X[j + q M/8], already in the
+// thread's registers, so input and output are both in natural order.
+//
+// Radix 8 needs two exchanges for M = 512 (radix 4 needs four), which halves
+// the LDS traffic per element.  An exchange moves each 32-byte interval in two
+// 16-byte halves (real bounds, then imaginary bounds), so the exchange buffer is
+// M x 16 bytes.  When the group is one wavefront (M/8 <= 64) the exchanges need
+// no workgroup barrier: LDS operations of one wavefront complete in order.
+#pragma once
+#include "fft.hpp"
+
+namespace ssa {
+
+// Synchronisation of an exchange: a workgroup barrier, or within one wavefront
+// only an ordering point for the compiler (the hardware keeps a wavefront's LDS
+// operations in order).
+template <bool WAVE> __device__ __forceinline__ void xsync() {
+  if (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Multiplication by omega_8 = c (1 + i) and by omega_8^3 = c (-1 + i), with c a
+// point within e of 1/sqrt(2):  (x + i y)(1 + i) = (x - y) + i (x + y) and
+// (x + i y)(-1 + i) = -(x + y) + i (x - y); then c[u] is [c u.lo, c u.hi] widened
+// by e |u|max.
+__device__ __forceinline__ ci ci_mul_w8(const ci &z, double c, double e) {
+  const double un = ru_add(z.rn, z.ih), uh = ru_add(z.rh, z.in);  // u = x - y
+  const double wn = ru_add(z.rn, z.in), wh = ru_add(z.rh, z.ih);  // w = x + y
+  const double Eu = ru_mul(e, dmax(un, uh)), Ew = ru_mul(e, dmax(wn, wh));
+  return ci{ru_fma(c, un, Eu), ru_fma(c, uh, Eu), ru_fma(c, wn, Ew), ru_fma(c, wh, Ew)};
+}
+__device__ __forceinline__ ci ci_mul_w83(const ci &z, double c, double e) {
+  const double un = ru_add(z.rn, z.ih), uh = ru_add(z.rh, z.in);  // u = x - y
+  const double wn = ru_add(z.rn, z.in), wh = ru_add(z.rh, z.ih);  // w = x + y
+  const double Eu = ru_mul(e, dmax(un, uh)), Ew = ru_mul(e, dmax(wn, wh));
+  // re = -c w: bounds swap; im = c u
+  return ci{ru_fma(c, wh, Ew), ru_fma(c, wn, Ew), ru_fma(c, un, Eu), ru_fma(c, uh, Eu)};
+}
+
+// Length-8 DFT with omega_8 = e^{+2 pi i/8}, as two length-4 DFTs:
+// a_r = v_r + v_{r+4}, b_r = (v_r - v_{r+4}) omega_8^r (r < 4);
+// y_{2m} = DFT4(a)_m, y_{2m+1} = DFT4(b)_m.  Only omega_8 and omega_8^3 are
+// interval-inexact; omega_8^2 = i is a permutation.
+__device__ __forceinline__ void radix8(ci v[8], double c8, double e8) {
+  ci a[4], b[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    a[r] = ci_add(v[r], v[r + 4]);
+    b[r] = ci_sub(v[r], v[r + 4]);
+  }
+  b[1] = ci_mul_w8(b[1], c8, e8);
+  b[2] = ci_mul_i(b[2]);
+  b[3] = ci_mul_w83(b[3], c8, e8);
+  radix4(a);
+  radix4(b);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    v[2 * m] = a[m];
+    v[2 * m + 1] = b[m];
+  }
+}
+
+// Half-element LDS helpers: buffer of double2, element i at h[i * is].
+__device__ __forceinline__ void hput(double2 *h, int idx, double x, double y) {
+  h[idx] = make_double2(x, y);
+}
+
+// Move the 8 values of this thread to positions wpos(q) and read back the
+// values at rpos(r) = j + r M/8, in two 16-byte rounds.
+template <bool WAVE, class W>
+__device__ __forceinline__ void exchange8(ci v[8], int j, int M8, double2 *h, int is, W wpos) {
+  double2 t[8];
+  xsync<WAVE>();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) hput(h, wpos(q) * is, v[q].rn, v[q].rh);
+  xsync<WAVE>();
+#pragma unroll
+  for (int r = 0; r < 8; ++r) t[r] = h[(j + r * M8) * is];
+  xsync<WAVE>();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) hput(h, wpos(q) * is, v[q].in, v[q].ih);
+  xsync<WAVE>();
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const double2 u = h[(j + r * M8) * is];
+    v[r] = ci{t[r].x, t[r].y, u.x, u.y};
+  }
+}
+
+// Forward interval DFT of the group's M = 2^logM elements (logM >= 3).
+// `h` points at element 0 of this group's half-element exchange buffer; element
+// i lives at h[i * is].  With WAVE the group must be exactly the lanes of (part
+// of) one wavefront; otherwise every thread of the workgroup must call this with
+// the same M.
+template <bool WAVE>
+__device__ __forceinline__ void fft8_group(ci v[8], int j, int logM, double2 *h, int is,
+                                           const twtab &T) {
+  const int M8 = 1 << (logM - 3);
+  const double2 w8 = T.tab[1u << (T.log_ntab - 3)];  // omega_8 from the table
+  const double c8 = w8.x, e8 = T.e;                  // |1/sqrt 2 - c8| <= e
+  int logNs = 0;
+  const int first = logM % 3;
+  if (first == 1) {
+    // radix 2 (Ns = 1): this thread acts for positions jv = j + t M/8, t < 4,
+    // pairs (x[jv], x[jv + M/2]) = (v_t, v_{t+4}); results to y[2 jv], y[2 jv + 1].
+    ci y[8];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      y[2 * t] = ci_add(v[t], v[t + 4]);
+      y[2 * t + 1] = ci_sub(v[t], v[t + 4]);
+    }
+    exchange8<WAVE>(y, j, M8, h, is, [&](int q) { return 2 * (j + (q >> 1) * M8) + (q & 1); });
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = y[r];
+    logNs = 1;
+  } else if (first == 2) {
+    // radix 4 (Ns = 1): positions jv = j + t M/8, t < 2, elements
+    // x[jv + s M/4] = v_{t + 2 s}; results to y[4 jv + q].
+    ci y[8];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      ci u[4] = {v[t], v[t + 2], v[t + 4], v[t + 6]};
+      radix4(u);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) y[4 * t + q] = u[q];
+    }
+    exchange8<WAVE>(y, j, M8, h, is, [&](int q) { return 4 * (j + (q >> 2) * M8) + (q & 3); });
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = y[r];
+    logNs = 2;
+  }
+  for (;;) {
+    const int Ns = 1 << logNs;
+    const int k = j & (Ns - 1);
+    if (logNs > 0) {
+      const int sh = T.log_ntab - (logNs + 3);
+#pragma unroll
+      for (int r = 1; r < 8; ++r) v[r] = apply_tw(v[r], T, static_cast<uint32_t>(r * k) << sh);
+    }
+    radix8(v, c8, e8);
+    if (logNs + 3 == logM) break;  // last stage: X[j + q M/8] = v[q]
+    const int base = ((j - k) << 3) + k;
+    exchange8<WAVE>(v, j, M8, h, is, [&](int q) { return base + q * Ns; });
+    logNs += 3;
+  }
+}
+
+}  // namespace ssa

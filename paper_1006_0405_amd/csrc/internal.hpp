@@ -46,9 +46,10 @@ static constexpr int CARRY_TILE = CARRY_THREADS * CARRY_CHUNKS;
 // one tile do not contend with the publication of its neighbours.
 static constexpr uint32_t TILE_WORD_STRIDE = 32;
 
-// Largest transform done by one workgroup holding everything in LDS.
+// Largest transform done by one workgroup holding everything in LDS, and the
+// smallest transform length (shorter products are zero-padded to it).
 static constexpr int SMALL_MAX_LOG = 12;
-static constexpr int SMALL_MIN_LOG = 8;
+static constexpr int SMALL_MIN_LOG = 9;
 
 struct launch_cfg {
   int log_n1;  // column transform length (multi-pass)

@@ -20,7 +20,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "fft.hpp"
+#include "fft8.hpp"
 #include "internal.hpp"
 
 namespace ssa {
@@ -219,80 +219,84 @@ __device__ __forceinline__ ci separated_product(const ci &Z, const ci &W) {
 }
 
 // ---------------------------------------------------------------------------
-// k_small: the whole product in one workgroup of N/4 threads, N = 2^log_n,
-// 2^8 <= N <= 2^12.  LDS: N complex intervals (reused for the coefficients).
+// k_small: the whole product in one workgroup of N/8 threads, N = 2^log_n,
+// 2^9 <= N <= 2^12.  LDS: N half-elements (16 B) for the exchanges, reused for
+// the coefficients.
 
-__global__ __launch_bounds__(1024) void k_small(const task *tasks, int log_n, int bits, int mode,
-                                                int pack, twtab T, double *dbg) {
-  extern __shared__ ci lds[];
-  __shared__ cert_shared sh;
-  __shared__ uint32_t sh_waves[16];
-  const uint32_t z = enter_round_up();
-  const task tk = after_mode(tasks, z)[blockIdx.x];
-  T.tab = after_mode(T.tab, z);
-  const int Q = 1 << (log_n - 2);
+template <bool WAVE>
+__device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, int mode, int pack,
+                                           const twtab &T, double *dbg, double2 *h,
+                                           cert_shared &sh, uint32_t *sh_waves) {
+  const int M8 = 1 << (log_n - 3);
+  const uint32_t mask = (1u << log_n) - 1u;
   const int j = threadIdx.x;
-  if (j == 0) sh = cert_shared{0ull, 0ull, 0u, 0u};
-
-  ci va[4];
+  ci va[8];
   if (pack) {  // one transform of z = a + i b, then separation
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t i = j + r * Q;
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t i = j + r * M8;
       const double da = static_cast<double>(digit(tk.a, tk.nda, i, bits));
       const double db = static_cast<double>(digit(tk.b, tk.ndb, i, bits));
       va[r] = ci{-da, da, -db, db};
     }
-    fft_group(va, j, log_n, lds, 1, T);
-    __syncthreads();
+    fft8_group<WAVE>(va, j, log_n, h, 1, T);
+    // partners Z_{-k}: real halves, then imaginary halves
+    double2 pr[8];
+    xsync<WAVE>();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) lds_put(lds, j + r * Q, va[r]);
-    __syncthreads();
-    const uint32_t mask = (1u << log_n) - 1u;
+    for (int r = 0; r < 8; ++r) h[j + r * M8] = make_double2(va[r].rn, va[r].rh);
+    xsync<WAVE>();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t k = j + r * Q;
-      const ci W = ci_conj(lds_get(lds, (0u - k) & mask));
+    for (int r = 0; r < 8; ++r) pr[r] = h[(0u - static_cast<uint32_t>(j + r * M8)) & mask];
+    xsync<WAVE>();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) h[j + r * M8] = make_double2(va[r].in, va[r].ih);
+    xsync<WAVE>();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const double2 pi = h[(0u - static_cast<uint32_t>(j + r * M8)) & mask];
+      const ci W{pr[r].x, pr[r].y, pi.y, pi.x};  // conj(Z_{-k})
       va[r] = ci_conj(separated_product(va[r], W));
     }
   } else {  // one transform per operand, pointwise product
-    ci vb[4];
+    ci vb[8];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t i = j + r * Q;
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t i = j + r * M8;
       va[r] = ci_thin_real(static_cast<double>(digit(tk.a, tk.nda, i, bits)));
       vb[r] = ci_thin_real(static_cast<double>(digit(tk.b, tk.ndb, i, bits)));
     }
-    fft_group(va, j, log_n, lds, 1, T);
-    fft_group(vb, j, log_n, lds, 1, T);
+    fft8_group<WAVE>(va, j, log_n, h, 1, T);
+    fft8_group<WAVE>(vb, j, log_n, h, 1, T);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) va[r] = ci_conj(ci_mul(va[r], vb[r]));
+    for (int r = 0; r < 8; ++r) va[r] = ci_conj(ci_mul(va[r], vb[r]));
   }
-  fft_group(va, j, log_n, lds, 1, T);
+  fft8_group<WAVE>(va, j, log_n, h, 1, T);
   const double scale = ldexp(1.0, -log_n);
   cert_acc acc{0.0, 0u, 0u, 0u};
-  unsigned long long cv[4];
+  unsigned long long cv[8];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const uint32_t i = j + r * Q;
+  for (int r = 0; r < 8; ++r) {
+    const uint32_t i = j + r * M8;
     const ci v = ci_scale(ci_conj(va[r]), scale);
     if (dbg != nullptr && blockIdx.x == 0) dbg_store(dbg, i, v);
     cv[r] = certify(v, i, tk.L, mode, acc);
   }
   cert_reduce(sh, acc);
   __syncthreads();  // LDS free again; counters final
-  unsigned long long *cl = reinterpret_cast<unsigned long long *>(lds);
+  unsigned long long *cl = reinterpret_cast<unsigned long long *>(h);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) cl[j + r * Q] = cv[r];
+  for (int r = 0; r < 8; ++r) cl[j + r * M8] = cv[r];
   __syncthreads();
   const bool failed = (sh.too_wide + sh.internal) != 0u;
   const uint32_t L = tk.L;
   const uint32_t nout = tk.na + tk.nb;
+  // waves = N/512, 9 chunks of 64 per wave cover 9N/8 >= N + 1 >= nout positions
   if (bits == 8) {
     auto C = [&](long long q) -> unsigned long long {
       return (q >= 0 && q < static_cast<long long>(L)) ? cl[q] : 0ull;
     };
-    carry_block<8>(C, 0, nout, tk.out, failed, [](uint32_t, uint32_t) { return 0u; }, sh_waves);
+    carry_block<9>(C, 0, nout, tk.out, failed, [](uint32_t, uint32_t) { return 0u; }, sh_waves);
   } else {
     auto C = [&](long long q) -> unsigned long long {
       if (q < 0) return 0ull;
@@ -301,9 +305,9 @@ __global__ __launch_bounds__(1024) void k_small(const task *tasks, int log_n, in
       const unsigned long long hi = i1 < static_cast<long long>(L) ? cl[i1] : 0ull;
       return lo + 16ull * hi;
     };
-    carry_block<8>(C, 0, nout, tk.out, failed, [](uint32_t, uint32_t) { return 0u; }, sh_waves);
+    carry_block<9>(C, 0, nout, tk.out, failed, [](uint32_t, uint32_t) { return 0u; }, sh_waves);
   }
-  if (j == 0) {
+  if (threadIdx.x == 0) {
     dev_stats *st = tk.st;
     st->max_rad_bits = sh.rad_bits;
     st->half_int = sh.half;
@@ -312,6 +316,22 @@ __global__ __launch_bounds__(1024) void k_small(const task *tasks, int log_n, in
     st->carry_err = 0u;
     st->ticket = 0u;
   }
+}
+
+__global__ __launch_bounds__(512) void k_small(const task *tasks, int log_n, int bits, int mode,
+                                               int pack, twtab T, double *dbg) {
+  extern __shared__ double2 hbuf[];
+  __shared__ cert_shared sh;
+  __shared__ uint32_t sh_waves[8];
+  const uint32_t z = enter_round_up();
+  const task tk = after_mode(tasks, z)[blockIdx.x];
+  T.tab = after_mode(T.tab, z);
+  if (threadIdx.x == 0) sh = cert_shared{0ull, 0ull, 0u, 0u};
+  __syncthreads();
+  if (log_n <= 9)
+    small_body<true>(tk, log_n, bits, mode, pack, T, dbg, hbuf, sh, sh_waves);
+  else
+    small_body<false>(tk, log_n, bits, mode, pack, T, dbg, hbuf, sh, sh_waves);
 }
 
 // ---------------------------------------------------------------------------
@@ -331,37 +351,39 @@ __device__ __forceinline__ ci apply_pass_tw(const ci &v, const twtab &T, uint32_
   return ci_twiddle(v, w.c, w.s, w.e);
 }
 
+// Statistics and carry-scan state of a product are reset by its first pass.
+__device__ __forceinline__ void reset_product_state(const task &tk) {
+  if (threadIdx.x == 0) {
+    tk.st->max_rad_bits = 0ull;
+    tk.st->half_int = 0ull;
+    tk.st->too_wide = 0u;
+    tk.st->internal = 0u;
+    tk.st->carry_err = 0u;
+    tk.st->ticket = 0u;
+  }
+  for (uint32_t t = threadIdx.x; t < tk.ntiles; t += blockDim.x) tk.tiles[t * TILE_WORD_STRIDE] = 0u;
+}
+
 // Columns: thread (c, j) with c = tid % C fastest, so that the C columns of a
-// workgroup are adjacent in memory.  grid = (N2 / C, 2 operands, tasks).
-__global__ __launch_bounds__(1024) void k_col_fwd(const task *tasks, int log_n1, int log_n2,
-                                                  int C, int bits, int pack, twtab T) {
-  extern __shared__ ci lds[];
+// workgroup are adjacent in memory.  grid = (N2 / C, 1 (packed) or 2, tasks).
+__global__ __launch_bounds__(512) void k_col_fwd(const task *tasks, int log_n1, int log_n2,
+                                                 int C, int bits, int pack, twtab T) {
+  extern __shared__ double2 hbuf[];
   const uint32_t z = enter_round_up();
   const task tk = after_mode(tasks, z)[blockIdx.z];
   T.tab = after_mode(T.tab, z);
   const int log_n = log_n1 + log_n2;
-  const uint32_t N2 = 1u << log_n2;
-  const int Q = 1 << (log_n1 - 2);
+  const int M8 = 1 << (log_n1 - 3);
   const int c = threadIdx.x % C, j = threadIdx.x / C;
   const uint32_t n2 = blockIdx.x * C + c;
   const bool opb = blockIdx.y != 0;
-  if (blockIdx.x == 0 && !opb) {  // reset this product's statistics and scan state
-    if (threadIdx.x == 0) {
-      tk.st->max_rad_bits = 0ull;
-      tk.st->half_int = 0ull;
-      tk.st->too_wide = 0u;
-      tk.st->internal = 0u;
-      tk.st->carry_err = 0u;
-      tk.st->ticket = 0u;
-    }
-    for (uint32_t t = threadIdx.x; t < tk.ntiles; t += blockDim.x) tk.tiles[t * TILE_WORD_STRIDE] = 0u;
-  }
+  if (blockIdx.x == 0 && !opb) reset_product_state(tk);
   const uint8_t *p = opb ? tk.b : tk.a;
   const uint32_t nd = opb ? tk.ndb : tk.nda;
-  ci v[4];
+  ci v[8];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const uint32_t n1 = j + r * Q;
+  for (int r = 0; r < 8; ++r) {
+    const uint32_t n1 = j + r * M8;
     const uint32_t i = (n1 << log_n2) + n2;
     if (pack) {  // z = a + i b: both real operands in one complex transform
       const double da = static_cast<double>(digit(tk.a, tk.nda, i, bits));
@@ -371,151 +393,154 @@ __global__ __launch_bounds__(1024) void k_col_fwd(const task *tasks, int log_n1,
       v[r] = ci_thin_real(static_cast<double>(digit(p, nd, i, bits)));
     }
   }
-  fft_group(v, j, log_n1, lds + c, C, T);
+  fft8_group<false>(v, j, log_n1, hbuf + c, C, T);
   ci *Y = opb ? tk.yb : tk.ya;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t k1 = j + q * Q;
-    const ci w = apply_pass_tw(v[q], T, n2, k1, log_n);
-    gst(Y, (static_cast<size_t>(k1) << log_n2) + n2, w);
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t k1 = j + q * M8;
+    gst(Y, (static_cast<size_t>(k1) << log_n2) + n2, apply_pass_tw(v[q], T, n2, k1, log_n));
   }
 }
 
-// Rows: R rows k1 per workgroup, N2/4 threads per row.  grid = (N1 / R, tasks).
-__global__ __launch_bounds__(512) void k_row(const task *tasks, int log_n1, int log_n2, int R,
-                                              twtab T) {
-  extern __shared__ ci lds[];
-  const uint32_t z = enter_round_up();
-  const task tk = after_mode(tasks, z)[blockIdx.y];
-  T.tab = after_mode(T.tab, z);
+// Rows (one transform per operand): R rows k1 per workgroup, N2/8 threads per
+// row.  grid = (N1 / R, tasks).
+template <bool WAVE>
+__device__ __forceinline__ void row_body(const task &tk, int log_n1, int log_n2, int R,
+                                         const twtab &T, double2 *hbuf) {
   const int log_n = log_n1 + log_n2;
-  const int Q = 1 << (log_n2 - 2);
-  const int g = threadIdx.x / Q, j = threadIdx.x % Q;
+  const int M8 = 1 << (log_n2 - 3);
+  const int g = threadIdx.x / M8, j = threadIdx.x % M8;
   const uint32_t k1 = blockIdx.x * R + g;
-  ci *lg = lds + (static_cast<size_t>(g) << log_n2);
+  double2 *hg = hbuf + (static_cast<size_t>(g) << log_n2);
   const size_t row = static_cast<size_t>(k1) << log_n2;
-  ci va[4], vb[4];
+  ci va[8], vb[8];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    va[r] = gld(tk.ya, row + j + r * Q);
-    vb[r] = gld(tk.yb, row + j + r * Q);
+  for (int r = 0; r < 8; ++r) {
+    va[r] = gld(tk.ya, row + j + r * M8);
+    vb[r] = gld(tk.yb, row + j + r * M8);
   }
-  fft_group(va, j, log_n2, lg, 1, T);
-  fft_group(vb, j, log_n2, lg, 1, T);
+  fft8_group<WAVE>(va, j, log_n2, hg, 1, T);
+  fft8_group<WAVE>(vb, j, log_n2, hg, 1, T);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) va[r] = ci_conj(ci_mul(va[r], vb[r]));
-  fft_group(va, j, log_n2, lg, 1, T);
+  for (int r = 0; r < 8; ++r) va[r] = ci_conj(ci_mul(va[r], vb[r]));
+  fft8_group<WAVE>(va, j, log_n2, hg, 1, T);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t n2 = j + q * Q;
-    const ci w = ci_conj(apply_pass_tw(va[q], T, n2, k1, log_n));
-    gst(tk.ya, row + n2, w);
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t n2 = j + q * M8;
+    gst(tk.ya, row + n2, ci_conj(apply_pass_tw(va[q], T, n2, k1, log_n)));
   }
 }
 
-// Row pairs for the packed transform: group g of N2/4 threads handles the
-// rows k1 and N1 - k1 (pair p >= 1, k1 = p) or the two self-paired rows 0 and
-// N1/2 (p = 0).  Index k = k1 + N1 k2 has -k = (N1 - k1) + N1 (N2 - 1 - k2) for
-// k1 > 0 and -k = N1 ((N2 - k2) mod N2) for k1 = 0, so the partner Z_{-k} of
-// every element of a pair lies in the same pair.  For a general pair only the
-// products of row k1 are formed; row N1 - k1 gets C_{-k} = conj(C_k), exact
-// because the convolution is real.  Per row: forward length-N2 DFT, the
-// separated pointwise product, the length-N2 DFT of the conjugate and the
-// conjugate inter-pass twiddle.  grid = (N1 / 2 / G, tasks).
-__global__ __launch_bounds__(512) void k_row_pair(const task *tasks, int log_n1, int log_n2,
-                                                  int G, twtab T) {
-  extern __shared__ ci lds[];
+__global__ __launch_bounds__(512) void k_row(const task *tasks, int log_n1, int log_n2, int R,
+                                             twtab T) {
+  extern __shared__ double2 hbuf[];
   const uint32_t z = enter_round_up();
   const task tk = after_mode(tasks, z)[blockIdx.y];
   T.tab = after_mode(T.tab, z);
+  if (log_n2 <= 9)
+    row_body<true>(tk, log_n1, log_n2, R, T, hbuf);
+  else
+    row_body<false>(tk, log_n1, log_n2, R, T, hbuf);
+}
+
+// Row pairs for the packed transform.  Index k = k1 + N1 k2 has
+// -k = (N1 - k1) + N1 (N2 - 1 - k2) for k1 > 0 and -k = N1 ((N2 - k2) mod N2) for
+// k1 = 0, so the partner Z_{-k} of every element of rows k1 and N1 - k1 lies in
+// the other row (pair p >= 1, rows p and N1 - p), and rows 0 and N1/2 are their
+// own partners (pair 0).  A workgroup holds G pairs, each as two row groups of
+// N2/8 threads.  Per row: forward length-N2 DFT, separated pointwise product
+// with the partner row, length-N2 DFT of the conjugate, conjugate inter-pass
+// twiddle.  grid = (N1 / 2 / G, tasks).
+template <bool WAVE>
+__device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int log_n2, int G,
+                                              const twtab &T, double2 *hbuf) {
   const int log_n = log_n1 + log_n2;
   const uint32_t N1 = 1u << log_n1, N2 = 1u << log_n2;
-  const int Q = 1 << (log_n2 - 2);
-  const int g = threadIdx.x / Q, j = threadIdx.x % Q;
+  const int M8 = 1 << (log_n2 - 3);
+  const int rg = threadIdx.x / M8;  // row group in the workgroup
+  const int j = threadIdx.x % M8;
+  const int g = rg >> 1, role = rg & 1;
   const uint32_t p = blockIdx.x * G + g;
-  const bool self = p == 0;  // rows 0 and N1/2, each its own partner
-  const uint32_t k1a = p, k1b = self ? N1 / 2 : N1 - p;
-  ci *L0 = lds + (static_cast<size_t>(g) << log_n2);
-  const size_t rowA = static_cast<size_t>(k1a) << log_n2, rowB = static_cast<size_t>(k1b) << log_n2;
-  ci va[4], vb[4];
+  const bool self = p == 0;
+  const uint32_t k1 = role == 0 ? p : (self ? N1 / 2 : N1 - p);
+  double2 *hown = hbuf + (static_cast<size_t>(rg) << log_n2);
+  double2 *hpart = self ? hown : hbuf + (static_cast<size_t>(rg ^ 1) << log_n2);
+  const size_t row = static_cast<size_t>(k1) << log_n2;
+  ci v[8];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    va[r] = gld(tk.ya, rowA + j + r * Q);
-    vb[r] = gld(tk.ya, rowB + j + r * Q);
+  for (int r = 0; r < 8; ++r) v[r] = gld(tk.ya, row + j + r * M8);
+  fft8_group<WAVE>(v, j, log_n2, hown, 1, T);
+  // partner values, real halves then imaginary halves (workgroup barriers:
+  // the partner row may be another wavefront)
+  uint32_t src[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const uint32_t k2 = j + r * M8;
+    src[r] = k1 == 0 ? ((N2 - k2) & (N2 - 1)) : (N2 - 1 - k2);
   }
-  fft_group(va, j, log_n2, L0, 1, T);
-  fft_group(vb, j, log_n2, L0, 1, T);
-  // round 1: the partners of row k1 (from row N1 - k1, or from row 0 itself)
+  double2 pr[8];
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 4; ++r) lds_put(L0, j + r * Q, self ? va[r] : vb[r]);
+  for (int r = 0; r < 8; ++r) hown[j + r * M8] = make_double2(v[r].rn, v[r].rh);
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const uint32_t k2 = j + r * Q;
-    const uint32_t src = self ? ((N2 - k2) & (N2 - 1)) : (N2 - 1 - k2);
-    va[r] = separated_product(va[r], ci_conj(lds_get(L0, src)));
-  }
-  // round 2: row N1 - k1 from conj(C_k), or row N1/2 from its own partners
+  for (int r = 0; r < 8; ++r) pr[r] = hpart[src[r]];
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const uint32_t k2 = j + r * Q;
-    if (self)
-      lds_put(L0, k2, vb[r]);
-    else
-      lds_put(L0, N2 - 1 - k2, ci_conj(va[r]));
-  }
+  for (int r = 0; r < 8; ++r) hown[j + r * M8] = make_double2(v[r].in, v[r].ih);
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const uint32_t k2 = j + r * Q;
-    vb[r] = self ? separated_product(vb[r], ci_conj(lds_get(L0, N2 - 1 - k2))) : lds_get(L0, k2);
+  for (int r = 0; r < 8; ++r) {
+    const double2 pi = hpart[src[r]];
+    const ci W{pr[r].x, pr[r].y, pi.y, pi.x};  // conj(Z_{-k})
+    v[r] = ci_conj(separated_product(v[r], W));
   }
+  __syncthreads();  // the partner has read this row's buffer
+  fft8_group<WAVE>(v, j, log_n2, hown, 1, T);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    va[r] = ci_conj(va[r]);
-    vb[r] = ci_conj(vb[r]);
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t n2 = j + q * M8;
+    gst(tk.ya, row + n2, ci_conj(apply_pass_tw(v[q], T, n2, k1, log_n)));
   }
-  fft_group(va, j, log_n2, L0, 1, T);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t n2 = j + q * Q;
-    gst(tk.ya, rowA + n2, ci_conj(apply_pass_tw(va[q], T, n2, k1a, log_n)));
-  }
-  fft_group(vb, j, log_n2, L0, 1, T);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t n2 = j + q * Q;
-    gst(tk.ya, rowB + n2, ci_conj(apply_pass_tw(vb[q], T, n2, k1b, log_n)));
-  }
+}
+
+__global__ __launch_bounds__(512) void k_row_pair(const task *tasks, int log_n1, int log_n2,
+                                                  int G, twtab T) {
+  extern __shared__ double2 hbuf[];
+  const uint32_t z = enter_round_up();
+  const task tk = after_mode(tasks, z)[blockIdx.y];
+  T.tab = after_mode(T.tab, z);
+  if (log_n2 <= 9)
+    row_pair_body<true>(tk, log_n1, log_n2, G, T, hbuf);
+  else
+    row_pair_body<false>(tk, log_n1, log_n2, G, T, hbuf);
 }
 
 // Inverse columns + scale + certification.  grid = (N2 / C, tasks).
-__global__ __launch_bounds__(1024) void k_col_inv(const task *tasks, int log_n1, int log_n2, int C,
-                                                  int mode, twtab T, double *dbg) {
-  extern __shared__ ci lds[];
+__global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n1, int log_n2, int C,
+                                                 int mode, twtab T, double *dbg) {
+  extern __shared__ double2 hbuf[];
   __shared__ cert_shared sh;
   const uint32_t z = enter_round_up();
   const task tk = after_mode(tasks, z)[blockIdx.y];
   T.tab = after_mode(T.tab, z);
   const int log_n = log_n1 + log_n2;
-  const int Q = 1 << (log_n1 - 2);
+  const int M8 = 1 << (log_n1 - 3);
   const int c = threadIdx.x % C, j = threadIdx.x / C;
   const uint32_t n2 = blockIdx.x * C + c;
   if (threadIdx.x == 0) sh = cert_shared{0ull, 0ull, 0u, 0u};
-  ci v[4];
+  ci v[8];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const uint32_t k1 = j + r * Q;
+  for (int r = 0; r < 8; ++r) {
+    const uint32_t k1 = j + r * M8;
     v[r] = ci_conj(gld(tk.ya, (static_cast<size_t>(k1) << log_n2) + n2));
   }
-  fft_group(v, j, log_n1, lds + c, C, T);
+  fft8_group<false>(v, j, log_n1, hbuf + c, C, T);
   const double scale = ldexp(1.0, -log_n);
   cert_acc acc{0.0, 0u, 0u, 0u};
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t n1 = j + q * Q;
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t n1 = j + q * M8;
     const uint32_t i = (n1 << log_n2) + n2;
     const ci w = ci_scale(ci_conj(v[q]), scale);
     if (dbg != nullptr && blockIdx.y == 0) dbg_store(dbg, i, w);
@@ -696,8 +721,8 @@ static inline void mark(const timing_hook *hk, int kind, int phase) {
 hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bits, int cert_mode,
                         int pack, const twtab_host &tw, double *dbg, hipStream_t s,
                         const timing_hook *hk) {
-  const int threads = 1 << (log_n - 2);
-  const size_t lds = sizeof(ci) << log_n;
+  const int threads = 1 << (log_n - 3);
+  const size_t lds = sizeof(double2) << log_n;
   mark(hk, KIND_SMALL, 0);
   hipLaunchKernelGGL(k_small, dim3(ntasks), dim3(threads), lds, s, d_tasks, log_n, digit_bits,
                      cert_mode, pack, to_dev(tw), dbg);
@@ -712,8 +737,8 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
   const uint32_t N1 = 1u << l1, N2 = 1u << l2;
   const twtab T = to_dev(tw);
   {
-    const int threads = cfg.cols * static_cast<int>(N1 / 4);
-    const size_t lds = sizeof(ci) * N1 * cfg.cols;
+    const int threads = cfg.cols * static_cast<int>(N1 / 8);
+    const size_t lds = sizeof(double2) * N1 * cfg.cols;
     mark(hk, KIND_COL_FWD, 0);
     hipLaunchKernelGGL(k_col_fwd, dim3(N2 / cfg.cols, cfg.pack ? 1 : 2, ntasks), dim3(threads), lds,
                        s, d_tasks, l1, l2, cfg.cols, digit_bits, cfg.pack, T);
@@ -722,8 +747,8 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
     if (e != hipSuccess) return e;
   }
   if (cfg.pack) {
-    const int threads = cfg.rows * static_cast<int>(N2 / 4);
-    const size_t lds = sizeof(ci) * N2 * cfg.rows;
+    const int threads = 2 * cfg.rows * static_cast<int>(N2 / 8);
+    const size_t lds = sizeof(double2) * 2 * N2 * cfg.rows;
     mark(hk, KIND_ROW, 0);
     hipLaunchKernelGGL(k_row_pair, dim3(N1 / 2 / cfg.rows, ntasks), dim3(threads), lds, s, d_tasks,
                        l1, l2, cfg.rows, T);
@@ -731,8 +756,8 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   } else {
-    const int threads = cfg.rows * static_cast<int>(N2 / 4);
-    const size_t lds = sizeof(ci) * N2 * cfg.rows;
+    const int threads = cfg.rows * static_cast<int>(N2 / 8);
+    const size_t lds = sizeof(double2) * N2 * cfg.rows;
     mark(hk, KIND_ROW, 0);
     hipLaunchKernelGGL(k_row, dim3(N1 / cfg.rows, ntasks), dim3(threads), lds, s, d_tasks, l1, l2,
                        cfg.rows, T);
@@ -741,8 +766,8 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
     if (e != hipSuccess) return e;
   }
   {
-    const int threads = cfg.cols * static_cast<int>(N1 / 4);
-    const size_t lds = sizeof(ci) * N1 * cfg.cols;
+    const int threads = cfg.cols * static_cast<int>(N1 / 8);
+    const size_t lds = sizeof(double2) * N1 * cfg.cols;
     mark(hk, KIND_COL_INV, 0);
     hipLaunchKernelGGL(k_col_inv, dim3(N2 / cfg.cols, ntasks), dim3(threads), lds, s, d_tasks, l1,
                        l2, cfg.cols, cert_mode, T, dbg);

@@ -28,14 +28,14 @@ def test_library_exports_every_declared_entry_point():
 
 
 def test_fft_size_follows_the_fast_convolution_box():
-    # N = 2^ceil(log2(L)), L = digits(a) + digits(b) - 1, padded to at least 256
+    # N = 2^ceil(log2(L)), L = digits(a) + digits(b) - 1, padded to at least 512
     assert binding.fft_size(1024, 1024) == 2048
     assert binding.fft_size(75000, 75000) == 1 << 18
     assert binding.fft_size(1_000_000, 1_000_000, 4) == 1 << 22
-    assert binding.fft_size(1, 1) == 256
-    assert binding.fft_size(129, 1) == 256
-    assert binding.fft_size(130, 128) == 512
-    assert binding.fft_size(64, 64, 4) == 256
+    assert binding.fft_size(1, 1) == 512
+    assert binding.fft_size(257, 1) == 512
+    assert binding.fft_size(258, 256) == 1024
+    assert binding.fft_size(128, 128, 4) == 512
     assert binding.fft_size(0, 5) == 0
     assert binding.fft_size(5, 5, 7) == 0
 
