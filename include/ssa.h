@@ -134,6 +134,31 @@ ssa_status ssa_mul_batch(ssa_plan *plan, size_t count, const uint8_t *const *a, 
                          const uint8_t *const *b, const size_t *nb, uint8_t *const *out,
                          int *status_dev);
 
+/* ---- Launch shapes and the autotuner ----------------------------------------- */
+
+/* Launch shape of the three-pass path (transforms longer than 2^12) for one
+ * transform length 2^log_n: column transforms of length 2^log_n1 (rows of
+ * 2^(log_n - log_n1)), `cols` adjacent columns per column-pass workgroup, and
+ * `rows` rows (row pairs for the packed transform) per row-pass workgroup. */
+typedef struct {
+  int log_n1;
+  int cols;
+  int rows;
+  int reserved;
+} ssa_launch_config;
+
+ssa_status ssa_plan_get_config(const ssa_plan *plan, int log_n, ssa_launch_config *cfg_host);
+/* Rejects (SSA_INVALID_ARGUMENT) shapes that do not fit the kernels: workgroups
+ * over 512 threads or not whole wavefronts, LDS over 64 KiB, uneven grids. */
+ssa_status ssa_plan_set_config(ssa_plan *plan, int log_n, const ssa_launch_config *cfg_host);
+/* Times every valid shape for transforms of length 2^log_n (12 < log_n <= the
+ * plan's largest) on `count` synthetic products of that length (device memory
+ * allocated for the call and released), keeps the fastest in the plan and
+ * returns it with its time per batch of `count` products (milliseconds) and the
+ * number of shapes tried.  Synchronises the plan's stream. */
+ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_config *best_host,
+                             double *best_ms_host, int *tried_host);
+
 /* ---- Diagnostics used by the test-suite ------------------------------------ */
 
 /* Same computation as ssa_mul, and also writes the final enclosures of all N

@@ -32,7 +32,8 @@ SSA_CERTIFY_HALF_INTEGER = 1
 EXPORTS = ("ssa_fft_size", "ssa_plan_create", "ssa_plan_destroy", "ssa_mul", "ssa_get_stats",
            "ssa_batch_create", "ssa_batch_run", "ssa_batch_stats", "ssa_batch_destroy",
            "ssa_mul_batch", "ssa_debug_enclosures", "ssa_twiddle_table", "ssa_probe_directed",
-           "ssa_batch_run_timed", "ssa_batch_kernel_times")
+           "ssa_batch_run_timed", "ssa_batch_kernel_times", "ssa_plan_get_config",
+           "ssa_plan_set_config", "ssa_plan_autotune")
 KERNEL_KINDS = ("small", "col_fwd", "row", "col_inv", "carry", "status")
 
 
@@ -43,6 +44,14 @@ class SsaError(RuntimeError):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("digit_bits", ctypes.c_int),
                 ("certify_mode", ctypes.c_int), ("separate_transforms", ctypes.c_int)]
+
+
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("log_n1", ctypes.c_int), ("cols", ctypes.c_int), ("rows", ctypes.c_int),
+                ("reserved", ctypes.c_int)]
+
+    def as_dict(self):
+        return {"log_n1": self.log_n1, "cols": self.cols, "rows": self.rows}
 
 
 class Stats(ctypes.Structure):
@@ -98,6 +107,14 @@ def lib():
         L.ssa_twiddle_table.restype = ctypes.c_int
         L.ssa_twiddle_table.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int)]
+        L.ssa_plan_get_config.restype = ctypes.c_int
+        L.ssa_plan_get_config.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(LaunchConfig)]
+        L.ssa_plan_set_config.restype = ctypes.c_int
+        L.ssa_plan_set_config.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(LaunchConfig)]
+        L.ssa_plan_autotune.restype = ctypes.c_int
+        L.ssa_plan_autotune.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(LaunchConfig),
+                                        ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int)]
         L.ssa_probe_directed.restype = ctypes.c_int
         L.ssa_probe_directed.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]
         _lib = L
@@ -138,6 +155,7 @@ class Plan:
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.digit_bits = digit_bits
+        self.separate_transforms = bool(separate_transforms)
         opts = PlanOpts(SSA_FP64, digit_bits, certify_mode, int(bool(separate_transforms)))
         h = _vp()
         with torch.cuda.device(self.device):
@@ -186,6 +204,52 @@ class Plan:
                                           b.numel(), out.data_ptr(), enc.data_ptr(),
                                           ctypes.byref(st)), "ssa_debug_enclosures")
         return st.value, out, enc
+
+    def get_config(self, log_n):
+        c = LaunchConfig()
+        _check(lib().ssa_plan_get_config(self.handle, log_n, ctypes.byref(c)), "ssa_plan_get_config")
+        return c.as_dict()
+
+    def set_config(self, log_n, log_n1, cols, rows):
+        c = LaunchConfig(log_n1, cols, rows, 0)
+        _check(lib().ssa_plan_set_config(self.handle, log_n, ctypes.byref(c)), "ssa_plan_set_config")
+
+    def autotune(self, log_n, count=16, cache=None):
+        """Pick the fastest launch shape for transforms of length 2^log_n.  With
+        `cache` (a JSON file path) a shape measured before on the same GPU
+        architecture and plan options is reused instead of measured again."""
+        key = None
+        if cache:
+            import json
+            props = torch.cuda.get_device_properties(self.device)
+            key = "%s/log_n=%d/digit_bits=%d/separate=%d" % (
+                getattr(props, "gcnArchName", props.name), log_n, self.digit_bits,
+                int(self.separate_transforms))
+            try:
+                table = json.load(open(cache))
+            except (OSError, ValueError):
+                table = {}
+            if key in table:
+                c = table[key]
+                self.set_config(log_n, c["log_n1"], c["cols"], c["rows"])
+                return dict(c, cached=True)
+        best = LaunchConfig()
+        ms = ctypes.c_double(0)
+        tried = ctypes.c_int(0)
+        _check(lib().ssa_plan_autotune(self.handle, log_n, count, ctypes.byref(best),
+                                       ctypes.byref(ms), ctypes.byref(tried)), "ssa_plan_autotune")
+        res = dict(best.as_dict(), ms_per_batch=ms.value, batch=count, tried=tried.value,
+                   cached=False)
+        if cache:
+            import json
+            try:
+                table = json.load(open(cache))
+            except (OSError, ValueError):
+                table = {}
+            table[key] = res
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+        return res
 
     def twiddles(self):
         """(table Ntab x 2 float64 device tensor, error bound e, log2 Ntab)."""

@@ -50,6 +50,25 @@ launch_cfg default_cfg(int log_n, int pack) {
   return c;
 }
 
+// A launch shape is usable when every workgroup has at most 512 threads in
+// whole wavefronts, its LDS fits in 64 KiB, and the grids divide evenly.
+bool cfg_valid(const launch_cfg &c, int log_n) {
+  if (c.log_n1 < 6 || c.log_n1 > 11 || log_n - c.log_n1 < 6 || log_n - c.log_n1 > 11) return false;
+  if (c.log_n2 != log_n - c.log_n1) return false;
+  const int N1 = 1 << c.log_n1, N2 = 1 << c.log_n2;
+  const auto pow2 = [](int x) { return x > 0 && (x & (x - 1)) == 0; };
+  if (!pow2(c.cols) || N2 % c.cols) return false;
+  const int ct = c.cols * N1 / 8;
+  if (ct > 512 || ct % 64) return false;
+  if (static_cast<size_t>(N1) * c.cols * 16 > 65536) return false;
+  const int per = c.pack ? 2 : 1;
+  if (!pow2(c.rows) || (c.pack ? (N1 / 2) % c.rows : N1 % c.rows)) return false;
+  const int rt = per * c.rows * N2 / 8;
+  if (rt > 512 || rt % 64) return false;
+  if (static_cast<size_t>(per) * c.rows * N2 * 16 > 65536) return false;
+  return true;
+}
+
 bool hip_ok(hipError_t e) { return e == hipSuccess; }
 
 int status_from(const dev_stats &s) {
@@ -102,6 +121,7 @@ struct ssa_plan {
   task *h_task = nullptr;       // pinned
   dev_stats *h_stats = nullptr; // pinned
   ssa_stats last{};
+  launch_cfg cfg[MAX_LOG_N + 1];  // multi-pass launch shape per transform length
 };
 
 struct ssa_batch {
@@ -155,7 +175,7 @@ hipError_t enqueue_class(const ssa_plan *p, const task *d_tasks, int n, int log_
   const int pack = p->opts.separate_transforms ? 0 : 1;
   if (log_n <= SMALL_MAX_LOG)
     return launch_small(d_tasks, n, log_n, bits, mode, pack, tw_of(p), dbg, s);
-  return launch_multipass(d_tasks, n, log_n, default_cfg(log_n, pack), bits, mode, tw_of(p), dbg, s);
+  return launch_multipass(d_tasks, n, log_n, p->cfg[log_n], bits, mode, tw_of(p), dbg, s);
 }
 
 ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
@@ -233,6 +253,8 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
   p->max_nb = max_nb;
   p->log_nmax = log_nmax;
   p->log_ntab = log_nmax;
+  for (int l = SMALL_MAX_LOG + 1; l <= MAX_LOG_N; ++l)
+    p->cfg[l] = default_cfg(l, o.separate_transforms ? 0 : 1);
   const size_t N = size_t(1) << log_nmax;
   const size_t ntiles = (max_na + max_nb + CARRY_TILE - 1) / CARRY_TILE;
   bool ok = hip_ok(hipMalloc(&p->tab, sizeof(double2) << p->log_ntab)) &&
@@ -356,7 +378,7 @@ hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk) {
     const int pack = p->opts.separate_transforms ? 0 : 1;
     hipError_t e = l <= SMALL_MAX_LOG
                        ? launch_small(bt->d_tasks + s0, n, l, bits, mode, pack, tw_of(p), nullptr, s, hk)
-                       : launch_multipass(bt->d_tasks + s0, n, l, default_cfg(l, pack), bits, mode,
+                       : launch_multipass(bt->d_tasks + s0, n, l, p->cfg[l], bits, mode,
                                           tw_of(p), nullptr, s, hk);
     if (e != hipSuccess) return e;
     s0 = s1;
@@ -570,6 +592,129 @@ ssa_status ssa_mul_batch(ssa_plan *plan, size_t count, const uint8_t *const *a, 
   if (r == SSA_OK && !hip_ok(hipStreamSynchronize(plan->stream))) r = SSA_DEVICE_ERROR;
   ssa_batch_destroy(bt);
   return r;
+}
+
+// ---------------------------------------------------------------------------
+// Launch shapes and the autotuner
+
+static launch_cfg from_public(const ssa_launch_config &c, int log_n, int pack) {
+  launch_cfg r;
+  r.log_n1 = c.log_n1;
+  r.log_n2 = log_n - c.log_n1;
+  r.cols = c.cols;
+  r.rows = c.rows;
+  r.pack = pack;
+  return r;
+}
+
+ssa_status ssa_plan_get_config(const ssa_plan *plan, int log_n, ssa_launch_config *cfg) {
+  if (!plan || !cfg || log_n <= SMALL_MAX_LOG || log_n > MAX_LOG_N) return SSA_INVALID_ARGUMENT;
+  const launch_cfg &c = plan->cfg[log_n];
+  *cfg = ssa_launch_config{c.log_n1, c.cols, c.rows, 0};
+  return SSA_OK;
+}
+
+ssa_status ssa_plan_set_config(ssa_plan *plan, int log_n, const ssa_launch_config *cfg) {
+  if (!plan || !cfg || log_n <= SMALL_MAX_LOG || log_n > MAX_LOG_N) return SSA_INVALID_ARGUMENT;
+  const launch_cfg c = from_public(*cfg, log_n, plan->opts.separate_transforms ? 0 : 1);
+  if (!cfg_valid(c, log_n)) return SSA_INVALID_ARGUMENT;
+  plan->cfg[log_n] = c;
+  return SSA_OK;
+}
+
+ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_config *best,
+                             double *best_ms_host, int *tried_host) {
+  if (!plan || !best || !best_ms_host || log_n <= SMALL_MAX_LOG || log_n > plan->log_nmax ||
+      count < 1 || count > 4096)
+    return SSA_INVALID_ARGUMENT;
+  const int bits = plan->opts.digit_bits;
+  const int pack = plan->opts.separate_transforms ? 0 : 1;
+  // equal operands as long as the plan allows, at most 2^(log_n - 1) digits each;
+  // their transform length must be exactly 2^log_n
+  const size_t nbytes = std::min(std::min(plan->max_na, plan->max_nb),
+                                 (size_t(1) << (log_n - 1)) / (bits == 4 ? 2 : 1));
+  if (log_n_for(2 * digits(nbytes, bits) - 1) != log_n) return SSA_INVALID_ARGUMENT;
+  hipStream_t s = plan->stream;
+  uint8_t *dops = nullptr, *dout = nullptr;
+  const size_t ops_bytes = 2 * nbytes * count, out_bytes = 2 * nbytes * count;
+  if (!hip_ok(hipMalloc(&dops, ops_bytes)) || !hip_ok(hipMalloc(&dout, out_bytes))) {
+    hipFree(dops);
+    hipGetLastError();
+    return SSA_OUT_OF_MEMORY;
+  }
+  {  // pseudo-random operand bytes (xorshift), any content serves for timing
+    std::vector<uint8_t> h(ops_bytes);
+    uint64_t x = 0x9e3779b97f4a7c15ull;
+    for (auto &b : h) {
+      x ^= x << 13;
+      x ^= x >> 7;
+      x ^= x << 17;
+      b = static_cast<uint8_t>(x >> 24);
+    }
+    if (!hip_ok(hipMemcpy(dops, h.data(), ops_bytes, hipMemcpyHostToDevice))) {
+      hipFree(dops);
+      hipFree(dout);
+      return SSA_DEVICE_ERROR;
+    }
+  }
+  std::vector<const uint8_t *> pa(count), pb(count);
+  std::vector<uint8_t *> po(count);
+  std::vector<size_t> na(count, nbytes), nb(count, nbytes);
+  for (int i = 0; i < count; ++i) {
+    pa[i] = dops + 2 * nbytes * i;
+    pb[i] = dops + 2 * nbytes * i + nbytes;
+    po[i] = dout + 2 * nbytes * i;
+  }
+  ssa_batch *bt = nullptr;
+  ssa_status r = ssa_batch_create(plan, count, pa.data(), na.data(), pb.data(), nb.data(),
+                                  po.data(), &bt);
+  if (r != SSA_OK) {
+    hipFree(dops);
+    hipFree(dout);
+    return r;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  const launch_cfg keep = plan->cfg[log_n];
+  launch_cfg bestc = keep;
+  double bestms = 1e30;
+  int tried = 0;
+  bool ok = true;
+  for (int l1 = 6; l1 <= 11 && ok; ++l1)
+    for (int cols = 1; cols <= 32 && ok; cols *= 2)
+      for (int rows = 1; rows <= 64 && ok; rows *= 2) {
+        launch_cfg c{l1, log_n - l1, cols, rows, pack};
+        if (!cfg_valid(c, log_n)) continue;
+        plan->cfg[log_n] = c;
+        ok = hip_ok(enqueue_batch(bt, s, nullptr));  // warm-up
+        if (!ok) break;
+        const int reps = 3;
+        ok = hip_ok(hipEventRecord(e0, s));
+        for (int k = 0; k < reps && ok; ++k) ok = hip_ok(enqueue_batch(bt, s, nullptr));
+        ok = ok && hip_ok(hipEventRecord(e1, s)) && hip_ok(hipEventSynchronize(e1));
+        float ms = 0.f;
+        ok = ok && hip_ok(hipEventElapsedTime(&ms, e0, e1));
+        ++tried;
+        if (ok && ms / reps < bestms) {
+          bestms = ms / reps;
+          bestc = c;
+        }
+      }
+  plan->cfg[log_n] = ok ? bestc : keep;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  ssa_batch_destroy(bt);
+  hipFree(dops);
+  hipFree(dout);
+  if (!ok) {
+    hipGetLastError();
+    return SSA_DEVICE_ERROR;
+  }
+  *best = ssa_launch_config{bestc.log_n1, bestc.cols, bestc.rows, 0};
+  *best_ms_host = bestms;
+  if (tried_host) *tried_host = tried;
+  return SSA_OK;
 }
 
 }  // extern "C"

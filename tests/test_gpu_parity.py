@@ -348,3 +348,63 @@ def test_config3_batch_full():
     print("config3: %d products, max radius %.4f" % (len(A), max(rads)))
     bt.close()
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Launch shapes: products do not depend on the shape; the autotuner's choice is valid
+
+
+def _valid_shapes(log_n, packed=True):
+    out = []
+    for l1 in range(6, 12):
+        l2 = log_n - l1
+        if not 6 <= l2 <= 11:
+            continue
+        for cols in (1, 2, 4, 8, 16, 32):
+            for rows in (1, 2, 4, 8, 16, 32, 64):
+                ct = cols * (1 << l1) // 8
+                rt = (2 if packed else 1) * rows * (1 << l2) // 8
+                if (ct > 512 or ct % 64 or (1 << l1) * cols * 16 > 65536 or (1 << l2) % cols
+                        or rt > 512 or rt % 64 or (2 if packed else 1) * rows * (1 << l2) * 16 > 65536
+                        or ((1 << l1) // 2 if packed else (1 << l1)) % rows):
+                    continue
+                out.append((l1, cols, rows))
+    return out
+
+
+@pytest.mark.parametrize("separate", [False, True], ids=["packed", "separate"])
+@pytest.mark.parametrize("nbytes", [5000, 30000])
+def test_every_launch_shape_gives_the_same_product(nbytes, separate):
+    a, b = pair(nbytes + 11, nbytes, nbytes - 7)
+    plan = binding.Plan(nbytes, nbytes, separate_transforms=separate)
+    log_n = binding.fft_size(nbytes, nbytes).bit_length() - 1
+    want = int_product(a, b)
+    shapes = _valid_shapes(log_n, packed=not separate)
+    assert len(shapes) >= 4
+    for l1, cols, rows in shapes:
+        plan.set_config(log_n, l1, cols, rows)
+        assert plan.get_config(log_n) == {"log_n1": l1, "cols": cols, "rows": rows}
+        st, out = plan.mul(a, b)
+        assert st == binding.SSA_OK, (l1, cols, rows)
+        assert np.array_equal(_np(out), want), (l1, cols, rows)
+    with pytest.raises(binding.SsaError):
+        plan.set_config(log_n, 3, 1, 1)
+    with pytest.raises(binding.SsaError):
+        plan.set_config(log_n, log_n // 2, 3, 1)
+    plan.close()
+
+
+def test_autotuner_choice_is_used_and_correct(tmp_path):
+    n = 75000
+    plan = binding.Plan(n, n)
+    cache = str(tmp_path / "tune.json")
+    res = plan.autotune(18, count=8, cache=cache)
+    assert not res["cached"] and res["tried"] >= 4 and res["ms_per_batch"] > 0
+    print("autotune 2^18:", res)
+    again = plan.autotune(18, count=8, cache=cache)
+    assert again["cached"] and again["log_n1"] == res["log_n1"]
+    assert plan.get_config(18) == {k: res[k] for k in ("log_n1", "cols", "rows")}
+    a, b = pair(2, n)
+    st, out = plan.mul(a, b)
+    assert st == binding.SSA_OK and np.array_equal(_np(out), int_product(a, b))
+    plan.close()
