@@ -51,7 +51,8 @@ launch_cfg default_cfg(int log_n, int pack) {
 }
 
 // A launch shape is usable when every workgroup has at most 512 threads in
-// whole wavefronts, its LDS fits in 64 KiB, and the grids divide evenly.
+// whole wavefronts, its LDS (exchange buffers with one spare slot per 8
+// elements) fits in 80 KiB, and the grids divide evenly.
 bool cfg_valid(const launch_cfg &c, int log_n) {
   if (c.log_n1 < 6 || c.log_n1 > 11 || log_n - c.log_n1 < 6 || log_n - c.log_n1 > 11) return false;
   if (c.log_n2 != log_n - c.log_n1) return false;
@@ -60,12 +61,12 @@ bool cfg_valid(const launch_cfg &c, int log_n) {
   if (!pow2(c.cols) || N2 % c.cols) return false;
   const int ct = c.cols * N1 / 8;
   if (ct > 512 || ct % 64) return false;
-  if (static_cast<size_t>(N1) * c.cols * 16 > 65536) return false;
+  if ((N1 + N1 / 8) * static_cast<size_t>(c.cols) * 16 > 81920) return false;
   const int per = c.pack ? 2 : 1;
   if (!pow2(c.rows) || (c.pack ? (N1 / 2) % c.rows : N1 % c.rows)) return false;
   const int rt = per * c.rows * N2 / 8;
   if (rt > 512 || rt % 64) return false;
-  if (static_cast<size_t>(per) * c.rows * N2 * 16 > 65536) return false;
+  if (static_cast<size_t>(per) * c.rows * (N2 + N2 / 8) * 16 > 81920) return false;
   return true;
 }
 

@@ -75,7 +75,12 @@ __device__ __forceinline__ void radix8(ci v[8], double c8, double e8) {
   }
 }
 
-// Half-element LDS helpers: buffer of double2, element i at h[i * is].
+// Half-element LDS buffers hold element i at h[lpad(i) * is]: one spare slot
+// after every 8 elements, so that the stride-8 write patterns of the radix-8
+// stages spread over the LDS banks.  A buffer for M elements needs
+// lpad_size(M) slots.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr size_t lpad_size(size_t m) { return m + (m >> 3); }
 __device__ __forceinline__ void hput(double2 *h, int idx, double x, double y) {
   h[idx] = make_double2(x, y);
 }
@@ -87,24 +92,24 @@ __device__ __forceinline__ void exchange8(ci v[8], int j, int M8, double2 *h, in
   double2 t[8];
   xsync<WAVE>();
 #pragma unroll
-  for (int q = 0; q < 8; ++q) hput(h, wpos(q) * is, v[q].rn, v[q].rh);
+  for (int q = 0; q < 8; ++q) hput(h, lpad(wpos(q)) * is, v[q].rn, v[q].rh);
   xsync<WAVE>();
 #pragma unroll
-  for (int r = 0; r < 8; ++r) t[r] = h[(j + r * M8) * is];
+  for (int r = 0; r < 8; ++r) t[r] = h[lpad(j + r * M8) * is];
   xsync<WAVE>();
 #pragma unroll
-  for (int q = 0; q < 8; ++q) hput(h, wpos(q) * is, v[q].in, v[q].ih);
+  for (int q = 0; q < 8; ++q) hput(h, lpad(wpos(q)) * is, v[q].in, v[q].ih);
   xsync<WAVE>();
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const double2 u = h[(j + r * M8) * is];
+    const double2 u = h[lpad(j + r * M8) * is];
     v[r] = ci{t[r].x, t[r].y, u.x, u.y};
   }
 }
 
 // Forward interval DFT of the group's M = 2^logM elements (logM >= 3).
 // `h` points at element 0 of this group's half-element exchange buffer; element
-// i lives at h[i * is].  With WAVE the group must be exactly the lanes of (part
+// i lives at h[lpad(i) * is].  With WAVE the group must be exactly the lanes of (part
 // of) one wavefront; otherwise every thread of the workgroup must call this with
 // the same M.
 template <bool WAVE>

@@ -244,17 +244,17 @@ __device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, 
     double2 pr[8];
     xsync<WAVE>();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) h[j + r * M8] = make_double2(va[r].rn, va[r].rh);
+    for (int r = 0; r < 8; ++r) h[lpad(j + r * M8)] = make_double2(va[r].rn, va[r].rh);
     xsync<WAVE>();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) pr[r] = h[(0u - static_cast<uint32_t>(j + r * M8)) & mask];
+    for (int r = 0; r < 8; ++r) pr[r] = h[lpad((0u - static_cast<uint32_t>(j + r * M8)) & mask)];
     xsync<WAVE>();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) h[j + r * M8] = make_double2(va[r].in, va[r].ih);
+    for (int r = 0; r < 8; ++r) h[lpad(j + r * M8)] = make_double2(va[r].in, va[r].ih);
     xsync<WAVE>();
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      const double2 pi = h[(0u - static_cast<uint32_t>(j + r * M8)) & mask];
+      const double2 pi = h[lpad((0u - static_cast<uint32_t>(j + r * M8)) & mask)];
       const ci W{pr[r].x, pr[r].y, pi.y, pi.x};  // conj(Z_{-k})
       va[r] = ci_conj(separated_product(va[r], W));
     }
@@ -411,7 +411,7 @@ __device__ __forceinline__ void row_body(const task &tk, int log_n1, int log_n2,
   const int M8 = 1 << (log_n2 - 3);
   const int g = threadIdx.x / M8, j = threadIdx.x % M8;
   const uint32_t k1 = blockIdx.x * R + g;
-  double2 *hg = hbuf + (static_cast<size_t>(g) << log_n2);
+  double2 *hg = hbuf + static_cast<size_t>(g) * lpad_size(size_t(1) << log_n2);
   const size_t row = static_cast<size_t>(k1) << log_n2;
   ci va[8], vb[8];
 #pragma unroll
@@ -463,8 +463,9 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int lo
   const uint32_t p = blockIdx.x * G + g;
   const bool self = p == 0;
   const uint32_t k1 = role == 0 ? p : (self ? N1 / 2 : N1 - p);
-  double2 *hown = hbuf + (static_cast<size_t>(rg) << log_n2);
-  double2 *hpart = self ? hown : hbuf + (static_cast<size_t>(rg ^ 1) << log_n2);
+  const size_t rowslots = lpad_size(size_t(1) << log_n2);
+  double2 *hown = hbuf + static_cast<size_t>(rg) * rowslots;
+  double2 *hpart = self ? hown : hbuf + static_cast<size_t>(rg ^ 1) * rowslots;
   const size_t row = static_cast<size_t>(k1) << log_n2;
   ci v[8];
 #pragma unroll
@@ -481,17 +482,17 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int lo
   double2 pr[8];
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 8; ++r) hown[j + r * M8] = make_double2(v[r].rn, v[r].rh);
+  for (int r = 0; r < 8; ++r) hown[lpad(j + r * M8)] = make_double2(v[r].rn, v[r].rh);
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 8; ++r) pr[r] = hpart[src[r]];
+  for (int r = 0; r < 8; ++r) pr[r] = hpart[lpad(src[r])];
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 8; ++r) hown[j + r * M8] = make_double2(v[r].in, v[r].ih);
+  for (int r = 0; r < 8; ++r) hown[lpad(j + r * M8)] = make_double2(v[r].in, v[r].ih);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const double2 pi = hpart[src[r]];
+    const double2 pi = hpart[lpad(src[r])];
     const ci W{pr[r].x, pr[r].y, pi.y, pi.x};  // conj(Z_{-k})
     v[r] = ci_conj(separated_product(v[r], W));
   }
@@ -722,7 +723,7 @@ hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bi
                         int pack, const twtab_host &tw, double *dbg, hipStream_t s,
                         const timing_hook *hk) {
   const int threads = 1 << (log_n - 3);
-  const size_t lds = sizeof(double2) << log_n;
+  const size_t lds = sizeof(double2) * lpad_size(size_t(1) << log_n);
   mark(hk, KIND_SMALL, 0);
   hipLaunchKernelGGL(k_small, dim3(ntasks), dim3(threads), lds, s, d_tasks, log_n, digit_bits,
                      cert_mode, pack, to_dev(tw), dbg);
@@ -738,7 +739,7 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
   const twtab T = to_dev(tw);
   {
     const int threads = cfg.cols * static_cast<int>(N1 / 8);
-    const size_t lds = sizeof(double2) * N1 * cfg.cols;
+    const size_t lds = sizeof(double2) * lpad_size(N1) * cfg.cols;
     mark(hk, KIND_COL_FWD, 0);
     hipLaunchKernelGGL(k_col_fwd, dim3(N2 / cfg.cols, cfg.pack ? 1 : 2, ntasks), dim3(threads), lds,
                        s, d_tasks, l1, l2, cfg.cols, digit_bits, cfg.pack, T);
@@ -748,7 +749,7 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
   }
   if (cfg.pack) {
     const int threads = 2 * cfg.rows * static_cast<int>(N2 / 8);
-    const size_t lds = sizeof(double2) * 2 * N2 * cfg.rows;
+    const size_t lds = sizeof(double2) * 2 * lpad_size(N2) * cfg.rows;
     mark(hk, KIND_ROW, 0);
     hipLaunchKernelGGL(k_row_pair, dim3(N1 / 2 / cfg.rows, ntasks), dim3(threads), lds, s, d_tasks,
                        l1, l2, cfg.rows, T);
@@ -757,7 +758,7 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
     if (e != hipSuccess) return e;
   } else {
     const int threads = cfg.rows * static_cast<int>(N2 / 8);
-    const size_t lds = sizeof(double2) * N2 * cfg.rows;
+    const size_t lds = sizeof(double2) * lpad_size(N2) * cfg.rows;
     mark(hk, KIND_ROW, 0);
     hipLaunchKernelGGL(k_row, dim3(N1 / cfg.rows, ntasks), dim3(threads), lds, s, d_tasks, l1, l2,
                        cfg.rows, T);
@@ -767,7 +768,7 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
   }
   {
     const int threads = cfg.cols * static_cast<int>(N1 / 8);
-    const size_t lds = sizeof(double2) * N1 * cfg.cols;
+    const size_t lds = sizeof(double2) * lpad_size(N1) * cfg.cols;
     mark(hk, KIND_COL_INV, 0);
     hipLaunchKernelGGL(k_col_inv, dim3(N2 / cfg.cols, ntasks), dim3(threads), lds, s, d_tasks, l1,
                        l2, cfg.cols, cert_mode, T, dbg);

@@ -364,8 +364,10 @@ def _valid_shapes(log_n, packed=True):
             for rows in (1, 2, 4, 8, 16, 32, 64):
                 ct = cols * (1 << l1) // 8
                 rt = (2 if packed else 1) * rows * (1 << l2) // 8
-                if (ct > 512 or ct % 64 or (1 << l1) * cols * 16 > 65536 or (1 << l2) % cols
-                        or rt > 512 or rt % 64 or (2 if packed else 1) * rows * (1 << l2) * 16 > 65536
+                pad1 = (1 << l1) + (1 << l1) // 8
+                pad2 = (1 << l2) + (1 << l2) // 8
+                if (ct > 512 or ct % 64 or pad1 * cols * 16 > 81920 or (1 << l2) % cols
+                        or rt > 512 or rt % 64 or (2 if packed else 1) * rows * pad2 * 16 > 81920
                         or ((1 << l1) // 2 if packed else (1 << l1)) % rows):
                     continue
                 out.append((l1, cols, rows))
