@@ -103,6 +103,57 @@ def traffic_for(kernel, launches_products):
     return per_product * launches_products
 
 
+def measure_batch(binding, torch, digit_bits, steps, precision="fp64", A=None, B=None):
+    """Default: the 4096-product batch, operand lengths log-uniform in
+    [64, 16384] bytes (seed 3).  One graph launch per step; every product
+    checked once against CPython integers outside the timed region."""
+    from paper_1006_0405_amd.workloads import batch as make_batch
+    if A is None:
+        A, B = make_batch(seed=3)
+    plan = binding.Plan(max(len(a) for a in A), max(len(b) for b in B), digit_bits=digit_bits,
+                        precision=precision)
+    lengths = sorted({binding.fft_size(len(a), len(b), digit_bits).bit_length() - 1
+                      for a, b in zip(A, B)})
+    for lg in lengths:
+        if lg > 12:
+            plan.autotune(lg, count=32)
+    bt = binding.Batch(plan, A, B)
+    status = bt.run().cpu().numpy()
+    for i in range(len(A)):
+        want = (int.from_bytes(A[i].tobytes(), "little") *
+                int.from_bytes(B[i].tobytes(), "little")).to_bytes(len(A[i]) + len(B[i]), "little")
+        assert status[i] != binding.SSA_OK or bt.OUT[i].cpu().numpy().tobytes() == want, i
+    stats = bt.stats()
+    for _ in range(2):
+        bt.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bt.run()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    certified = int(np.sum(bt.status.cpu().numpy() == binding.SSA_OK))
+    res = {
+        "products": len(A),
+        "certified": certified,
+        "products_per_s": certified * steps / el,
+        "digits_per_s": sum(len(a) + len(b) for a, b in zip(A, B)) * steps / el,
+        "ms_per_batch": el / steps * 1e3,
+        "max_radius": max(s["max_radius"] for s in stats),
+        "digit_bits": digit_bits,
+        "precision": precision,
+    }
+    if precision != "fp64":
+        n_try = sum(1 for s in stats if s["fp32_attempt"])
+        n_fb = sum(1 for s in stats if s["fallback"])
+        res["fp32_attempted"] = n_try
+        res["fp32_certified"] = n_try - n_fb
+        res["fallback_rate"] = n_fb / max(1, n_try)  # re-runs per FP32 attempt
+    bt.close()
+    plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +161,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=64, help="products per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 4096-product uneven batch (FP64 base 256 and base 16)")
     ap.add_argument("--separate-transforms", action="store_true",
                     help="one forward FFT per operand (the fast convolution box literally) "
                          "instead of one FFT of a + i b")
@@ -149,7 +202,6 @@ def main():
             a, b = pair(2 + i // 2, NBYTES)
             A.append(a)
             Bs.append(b)
-    N = binding.fft_size(NBYTES, NBYTES)
     L = 2 * NBYTES - 1
     packed = not args.separate_transforms
     plan = binding.Plan(NBYTES, NBYTES, separate_transforms=not packed)
@@ -258,6 +310,24 @@ def main():
     }
     batch.close()
     plan.close()
+
+    if not args.no_batch:
+        steps = max(3, args.steps // 10)
+        for bits, base in ((8, "base256"), (4, "base16")):
+            r64 = measure_batch(binding, torch, bits, steps)
+            r32 = measure_batch(binding, torch, bits, steps, precision="fp32_fallback")
+            r32["speedup_vs_fp64"] = r32["products_per_s"] / r64["products_per_s"]
+            result["batch_fp64_" + base] = r64
+            result["batch_fp32_fallback_" + base] = r32
+        # inside the FP32 frontier: 8192 products of 100 x 100 bytes, base 16
+        # (L = 399, N = 512), where every FP32 attempt is expected to certify
+        from paper_1006_0405_amd.workloads import pair
+        A, B = zip(*[pair(50_000 + i, 100, 100) for i in range(8192)])
+        r64 = measure_batch(binding, torch, 4, steps, A=list(A), B=list(B))
+        r32 = measure_batch(binding, torch, 4, steps, "fp32_fallback", A=list(A), B=list(B))
+        r32["speedup_vs_fp64"] = r32["products_per_s"] / r64["products_per_s"]
+        result["frontier_100x100_base16_fp64"] = r64
+        result["frontier_100x100_base16_fp32_fallback"] = r32
 
     if not args.no_cpu_baseline:
         n = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))

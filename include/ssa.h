@@ -51,7 +51,13 @@ enum { SSA_FP64 = 0, SSA_FP32_FALLBACK = 1 };
 enum { SSA_CERTIFY_ONE_INTEGER = 0, SSA_CERTIFY_HALF_INTEGER = 1 };
 
 typedef struct {
-  int precision;           /* SSA_FP64 (the path of the paper)                         */
+  int precision;           /* SSA_FP64: the path of the paper, all in FP64 intervals.
+                              SSA_FP32_FALLBACK: products that the plan's length
+                              predictor admits first run their forward
+                              transform in FP32 midpoint-radius discs (circular
+                              containment sets, section 4; the rest stays FP64);
+                              any product that this attempt cannot certify is
+                              re-run on the device in FP64.  Same products.     */
   int digit_bits;          /* 8: base-256 digits (paper, section 3); 4: base 16        */
   int certify_mode;        /* SSA_CERTIFY_ONE_INTEGER: exactly one integer (section 1);
                               SSA_CERTIFY_HALF_INTEGER: additionally fail any enclosure
@@ -71,6 +77,9 @@ typedef struct {
   uint32_t carry_err;  /* carry-scan waits that timed out (must be 0)                  */
   uint32_t log_n;      /* transform length used, N = 2^log_n                           */
   int status;          /* ssa_status of the product                                    */
+  int fallback;        /* 1: the FP32 attempt failed and the FP64 re-run produced the
+                          result (SSA_FP32_FALLBACK plans only)                         */
+  int fp32_attempt;    /* 1: the product went through an FP32 attempt                  */
   int reserved;
 } ssa_stats;
 
@@ -98,6 +107,16 @@ void ssa_plan_destroy(ssa_plan *plan);
  * ssa_status.  On any status other than SSA_OK, out is zero-filled. */
 ssa_status ssa_mul(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
                    uint8_t *out, ssa_status *status);
+
+/* FP32 policy of an SSA_FP32_FALLBACK plan (the length predictor): a product
+ * tries FP32 first when its coefficient count L = digits(a) + digits(b) - 1 is
+ * at most max_coeffs (0 <= max_coeffs <= 4096; 0 disables the attempt) and its
+ * transform fits one workgroup (N <= 4096); all others run in FP64 directly.
+ * The plan starts with a default that depends on digit_bits.  force_fail = 1
+ * widens every FP32 disc so that each attempt fails (a test hook for the
+ * re-run).  SSA_INVALID_ARGUMENT for an FP64 plan or a value out of range.
+ * Batches created afterwards use the new policy. */
+ssa_status ssa_plan_set_fp32_policy(ssa_plan *plan, int max_coeffs, int force_fail);
 
 /* Statistics of the last ssa_mul on this plan. */
 ssa_status ssa_get_stats(const ssa_plan *plan, ssa_stats *stats_host);

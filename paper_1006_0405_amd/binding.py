@@ -25,6 +25,8 @@ STATUS_NAMES = {0: "OK", 1: "ENCLOSURE_TOO_WIDE", 2: "INVALID_ARGUMENT", 3: "OUT
                 4: "DEVICE_ERROR", 5: "INTERNAL_ERROR"}
 
 SSA_FP64 = 0
+SSA_FP32_FALLBACK = 1
+PRECISIONS = {"fp64": SSA_FP64, "fp32_fallback": SSA_FP32_FALLBACK}
 SSA_CERTIFY_ONE_INTEGER = 0
 SSA_CERTIFY_HALF_INTEGER = 1
 
@@ -33,7 +35,7 @@ EXPORTS = ("ssa_fft_size", "ssa_plan_create", "ssa_plan_destroy", "ssa_mul", "ss
            "ssa_batch_create", "ssa_batch_run", "ssa_batch_stats", "ssa_batch_destroy",
            "ssa_mul_batch", "ssa_debug_enclosures", "ssa_twiddle_table", "ssa_probe_directed",
            "ssa_batch_run_timed", "ssa_batch_kernel_times", "ssa_plan_get_config",
-           "ssa_plan_set_config", "ssa_plan_autotune")
+           "ssa_plan_set_config", "ssa_plan_autotune", "ssa_plan_set_fp32_policy")
 KERNEL_KINDS = ("small", "col_fwd", "row", "col_inv", "carry", "status")
 
 
@@ -58,7 +60,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("max_radius", ctypes.c_double), ("half_int", ctypes.c_uint64),
                 ("too_wide", ctypes.c_uint32), ("internal", ctypes.c_uint32),
                 ("carry_err", ctypes.c_uint32), ("log_n", ctypes.c_uint32),
-                ("status", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("status", ctypes.c_int), ("fallback", ctypes.c_int),
+                ("fp32_attempt", ctypes.c_int), ("reserved", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -115,6 +118,8 @@ def lib():
         L.ssa_plan_autotune.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(LaunchConfig),
                                         ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int)]
+        L.ssa_plan_set_fp32_policy.restype = ctypes.c_int
+        L.ssa_plan_set_fp32_policy.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
         L.ssa_probe_directed.restype = ctypes.c_int
         L.ssa_probe_directed.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]
         _lib = L
@@ -151,12 +156,16 @@ class Plan:
     """A plan for products with at most max_na x max_nb bytes."""
 
     def __init__(self, max_na, max_nb, digit_bits=8, certify_mode=SSA_CERTIFY_ONE_INTEGER,
-                 separate_transforms=False, stream=None, device=None):
+                 separate_transforms=False, precision="fp64", stream=None, device=None):
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.digit_bits = digit_bits
         self.separate_transforms = bool(separate_transforms)
-        opts = PlanOpts(SSA_FP64, digit_bits, certify_mode, int(bool(separate_transforms)))
+        if precision not in PRECISIONS:
+            raise SsaError("precision %r is not available (one of %s)" % (precision, sorted(PRECISIONS)))
+        self.precision = precision
+        opts = PlanOpts(PRECISIONS[precision], digit_bits, certify_mode,
+                        int(bool(separate_transforms)))
         h = _vp()
         with torch.cuda.device(self.device):
             _check(lib().ssa_plan_create(ctypes.byref(h), max_na, max_nb, ctypes.byref(opts),
@@ -191,6 +200,12 @@ class Plan:
         s = Stats()
         _check(lib().ssa_get_stats(self.handle, ctypes.byref(s)), "ssa_get_stats")
         return s.as_dict()
+
+    def set_fp32_policy(self, max_log_n, force_fail=False):
+        """FP32 first attempt for transforms up to 2^max_log_n (0: never);
+        force_fail makes every attempt fail (tests the FP64 re-run)."""
+        _check(lib().ssa_plan_set_fp32_policy(self.handle, int(max_log_n), int(bool(force_fail))),
+               "ssa_plan_set_fp32_policy")
 
     def debug_enclosures(self, a, b):
         """(status, out, enclosures N x 4 float64 {re_lo, re_hi, im_lo, im_hi})."""

@@ -72,6 +72,17 @@ bool cfg_valid(const launch_cfg &c, int log_n) {
 
 bool hip_ok(hipError_t e) { return e == hipSuccess; }
 
+// Default length predictor of the FP32 first attempt: the largest coefficient
+// count L for which random and all-0xFF operands still certify.  Radii add
+// linearly through the butterflies while magnitudes grow like a square root,
+// and the pointwise product multiplies a forward radius by the other
+// operand's transform, so the coefficient radius grows like n^1.5 U b^2 and
+// doubles with each extra radix-2 level: base-256 digits leave room only for
+// products of a few bytes, base 16 certifies while the transform has 512
+// points (L <= 511) and mostly fails from 1024 points on.
+constexpr uint32_t FP32_MAX_L_B256 = 7, FP32_MAX_L_B16 = 511;
+uint32_t default_fp32_max_L(int digit_bits) { return digit_bits == 8 ? FP32_MAX_L_B256 : FP32_MAX_L_B16; }
+
 int status_from(const dev_stats &s) {
   if (s.internal) return SSA_INTERNAL_ERROR;
   if (s.too_wide) return SSA_ENCLOSURE_TOO_WIDE;
@@ -90,6 +101,8 @@ ssa_stats to_public(const dev_stats &s, int log_n) {
   o.carry_err = s.carry_err;
   o.log_n = static_cast<uint32_t>(log_n);
   o.status = status_from(s);
+  o.fallback = static_cast<int>(s.fallback);
+  o.fp32_attempt = static_cast<int>(s.fp32);
   return o;
 }
 
@@ -105,6 +118,8 @@ struct ssa_plan {
   int device = 0;
   hipStream_t stream = nullptr;
   ssa_plan_opts opts{};
+  uint32_t fp32_max_L = 0;  // FP32 first attempt for products with L <= this (0: never)
+  int hooks = 0;         // test hooks (HOOK_FORCE_FP32_FAIL)
   size_t max_na = 0, max_nb = 0;
   int log_nmax = 0;
   // twiddles
@@ -169,14 +184,29 @@ void free_plan(ssa_plan *p) {
 
 twtab_host tw_of(const ssa_plan *p) { return twtab_host{p->tab, p->log_ntab, p->e}; }
 
-// Enqueue one product class: all tasks [d_tasks, d_tasks + n) share log_n.
-hipError_t enqueue_class(const ssa_plan *p, const task *d_tasks, int n, int log_n, double *dbg,
-                         hipStream_t s) {
+// The FP32 twiddle bound assumes a table error below 2^-47 (it always is, by
+// many orders of magnitude).
+bool fp32_first(const ssa_plan *p, uint64_t L, int log_n) {
+  return p->opts.precision == SSA_FP32_FALLBACK && log_n <= SMALL_MAX_LOG &&
+         L <= p->fp32_max_L && p->e < 0x1p-47;
+}
+
+// Enqueue one product class: all tasks [d_tasks, d_tasks + n) share log_n, and
+// the first n32 of them are marked for the FP32 first attempt.
+hipError_t enqueue_class(const ssa_plan *p, const task *d_tasks, int n, int n32, int log_n,
+                         double *dbg, hipStream_t s, const timing_hook *hk = nullptr) {
   const int bits = p->opts.digit_bits, mode = p->opts.certify_mode;
   const int pack = p->opts.separate_transforms ? 0 : 1;
-  if (log_n <= SMALL_MAX_LOG)
-    return launch_small(d_tasks, n, log_n, bits, mode, pack, tw_of(p), dbg, s);
-  return launch_multipass(d_tasks, n, log_n, p->cfg[log_n], bits, mode, tw_of(p), dbg, s);
+  if (log_n <= SMALL_MAX_LOG) {
+    if (n32 == 0)
+      return launch_small(d_tasks, n, log_n, bits, mode, pack, 0, 0, 0, tw_of(p), dbg, s, hk);
+    // FP32 attempt, then FP64 over the class except what the attempt certified
+    const hipError_t e =
+        launch_small(d_tasks, n32, log_n, bits, mode, pack, 1, 0, p->hooks, tw_of(p), dbg, s, hk);
+    if (e != hipSuccess) return e;
+    return launch_small(d_tasks, n, log_n, bits, mode, pack, 0, 1, 0, tw_of(p), dbg, s, hk);
+  }
+  return launch_multipass(d_tasks, n, log_n, p->cfg[log_n], bits, mode, tw_of(p), dbg, s, hk);
 }
 
 ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
@@ -205,10 +235,12 @@ ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b
   t.st = p->st;
   t.tiles = p->tiles;
   t.ntiles = static_cast<uint32_t>((na + nb + CARRY_TILE - 1) / CARRY_TILE);
+  t.fp32 = fp32_first(p, L, log_n) ? 1u : 0u;
   hipStream_t s = p->stream;
   if (!hip_ok(hipMemcpyAsync(p->d_task, p->h_task, sizeof(task), hipMemcpyHostToDevice, s)))
     return SSA_DEVICE_ERROR;
-  if (!hip_ok(enqueue_class(p, p->d_task, 1, log_n, dbg, s))) return SSA_DEVICE_ERROR;
+  if (!hip_ok(enqueue_class(p, p->d_task, 1, static_cast<int>(t.fp32), log_n, dbg, s)))
+    return SSA_DEVICE_ERROR;
   if (log_n > SMALL_MAX_LOG && !hip_ok(launch_carry(p->d_task, 1, t.ntiles, bits, s)))
     return SSA_DEVICE_ERROR;
   if (!hip_ok(hipMemcpyAsync(p->h_stats, p->st, sizeof(dev_stats), hipMemcpyDeviceToHost, s)))
@@ -236,7 +268,8 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
   if (opts) o = *opts;
   if (max_na == 0 || max_nb == 0 || (o.digit_bits != 8 && o.digit_bits != 4) ||
       (o.certify_mode != SSA_CERTIFY_ONE_INTEGER && o.certify_mode != SSA_CERTIFY_HALF_INTEGER) ||
-      o.precision != SSA_FP64 || (o.separate_transforms != 0 && o.separate_transforms != 1))
+      (o.precision != SSA_FP64 && o.precision != SSA_FP32_FALLBACK) ||
+      (o.separate_transforms != 0 && o.separate_transforms != 1))
     return SSA_INVALID_ARGUMENT;
   const uint64_t L = digits(max_na, o.digit_bits) + digits(max_nb, o.digit_bits) - 1;
   const int log_nmax = log_n_for(L);
@@ -250,6 +283,7 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
   p->stream = static_cast<hipStream_t>(stream);
   hipGetDevice(&p->device);
   p->opts = o;
+  if (o.precision == SSA_FP32_FALLBACK) p->fp32_max_L = default_fp32_max_L(o.digit_bits);
   p->max_na = max_na;
   p->max_nb = max_nb;
   p->log_nmax = log_nmax;
@@ -304,6 +338,15 @@ ssa_status ssa_debug_enclosures(ssa_plan *plan, const uint8_t *a, size_t na, con
                                 size_t nb, uint8_t *out, double *enc_dev, ssa_status *status) {
   if (!enc_dev) return SSA_INVALID_ARGUMENT;
   return run_single(plan, a, na, b, nb, out, enc_dev, status);
+}
+
+ssa_status ssa_plan_set_fp32_policy(ssa_plan *plan, int max_coeffs, int force_fail) {
+  if (!plan || plan->opts.precision != SSA_FP32_FALLBACK || max_coeffs < 0 ||
+      max_coeffs > (1 << SMALL_MAX_LOG) || (force_fail != 0 && force_fail != 1))
+    return SSA_INVALID_ARGUMENT;
+  plan->fp32_max_L = static_cast<uint32_t>(max_coeffs);
+  plan->hooks = force_fail ? HOOK_FORCE_FP32_FAIL : 0;
+  return SSA_OK;
 }
 
 ssa_status ssa_get_stats(const ssa_plan *plan, ssa_stats *stats_host) {
@@ -368,7 +411,7 @@ namespace {
 // multi-pass product, then the statuses.
 hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk) {
   const ssa_plan *p = bt->plan;
-  const int bits = p->opts.digit_bits, mode = p->opts.certify_mode;
+  const int bits = p->opts.digit_bits;
   size_t s0 = 0;
   const size_t count = bt->count;
   while (s0 < count) {
@@ -376,11 +419,9 @@ hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk) {
     const int l = static_cast<int>(bt->h_tasks[s0].log_n);
     while (s1 < count && static_cast<int>(bt->h_tasks[s1].log_n) == l) ++s1;
     const int n = static_cast<int>(s1 - s0);
-    const int pack = p->opts.separate_transforms ? 0 : 1;
-    hipError_t e = l <= SMALL_MAX_LOG
-                       ? launch_small(bt->d_tasks + s0, n, l, bits, mode, pack, tw_of(p), nullptr, s, hk)
-                       : launch_multipass(bt->d_tasks + s0, n, l, p->cfg[l], bits, mode,
-                                          tw_of(p), nullptr, s, hk);
+    int n32 = 0;
+    while (n32 < n && bt->h_tasks[s0 + n32].fp32) ++n32;  // marked tasks lead their class
+    const hipError_t e = enqueue_class(p, bt->d_tasks + s0, n, n32, l, nullptr, s, hk);
     if (e != hipSuccess) return e;
     s0 = s1;
   }
@@ -421,21 +462,26 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
     return SSA_INVALID_ARGUMENT;
   const int bits = plan->opts.digit_bits;
   std::vector<int> lg(count);
+  std::vector<char> f32(count);
   for (size_t i = 0; i < count; ++i) {
     if (!a[i] || !b[i] || !out[i] || na[i] == 0 || nb[i] == 0 || na[i] > plan->max_na ||
         nb[i] > plan->max_nb)
       return SSA_INVALID_ARGUMENT;
-    lg[i] = log_n_for(digits(na[i], bits) + digits(nb[i], bits) - 1);
+    const uint64_t L = digits(na[i], bits) + digits(nb[i], bits) - 1;
+    lg[i] = log_n_for(L);
+    f32[i] = fp32_first(plan, L, lg[i]) ? 1 : 0;
   }
   ssa_batch *bt = new (std::nothrow) ssa_batch();
   if (!bt) return SSA_OUT_OF_MEMORY;
   bt->plan = plan;
   bt->count = count;
-  // group by transform length, largest first
+  // group by transform length, largest first; within a length, the products
+  // marked for the FP32 attempt first
   bt->order.resize(count);
   for (size_t i = 0; i < count; ++i) bt->order[i] = static_cast<int>(i);
-  std::stable_sort(bt->order.begin(), bt->order.end(),
-                   [&](int x, int y) { return lg[x] > lg[y]; });
+  std::stable_sort(bt->order.begin(), bt->order.end(), [&](int x, int y) {
+    return lg[x] != lg[y] ? lg[x] > lg[y] : f32[x] > f32[y];
+  });
   // scratch sizes
   size_t arena_elems = 0, c_elems = 0, tiles = 0;
   for (size_t i = 0; i < count; ++i) {
@@ -475,6 +521,7 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
     t.ndb = static_cast<uint32_t>(digits(nb[i], bits));
     t.L = t.nda + t.ndb - 1;
     t.log_n = static_cast<uint32_t>(lg[i]);
+    t.fp32 = static_cast<uint32_t>(f32[i]);
     t.st = bt->stats + s;
     if (lg[i] > SMALL_MAX_LOG) {
       const size_t N = size_t(1) << lg[i];

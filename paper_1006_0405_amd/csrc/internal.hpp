@@ -16,7 +16,11 @@ struct dev_stats {
   unsigned int internal;            // enclosures that cannot be rigorous
   unsigned int carry_err;           // carry scan gave up waiting (never expected)
   unsigned int ticket;              // carry-scan tile ticket counter
+  unsigned int fallback;            // 1: the FP32 attempt failed, the FP64 re-run ran
+  unsigned int fp32;                // 1: an FP32 attempt was made
 };
+
+enum { HOOK_FORCE_FP32_FAIL = 1 };
 
 // One product as the kernels see it.  Sizes are in digits of the chosen base.
 struct task {
@@ -33,7 +37,7 @@ struct task {
   dev_stats *st;
   uint32_t *tiles;        // carry-scan tile status words
   uint32_t ntiles;
-  uint32_t pad;
+  uint32_t fp32;          // 1: FP32 first attempt, FP64 re-run on failure
 };
 
 enum { CERT_ONE_INTEGER = 0, CERT_HALF_INTEGER = 1 };
@@ -83,9 +87,11 @@ struct timing_hook {
 
 // dbg (nullable): N x 4 doubles {re_lo, re_hi, im_lo, im_hi} of the final
 // enclosures of task 0, written before certification.
+// fp32: FP32 first attempt over tasks that are all marked fp32; rerun: FP64
+// pass that follows it, skipping marked tasks that the attempt certified.
 hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bits, int cert_mode,
-                        int pack, const twtab_host &tw, double *dbg, hipStream_t s,
-                        const timing_hook *hk = nullptr);
+                        int pack, int fp32, int rerun, int hooks, const twtab_host &tw,
+                        double *dbg, hipStream_t s, const timing_hook *hk = nullptr);
 hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const launch_cfg &cfg,
                             int digit_bits, int cert_mode, const twtab_host &tw, double *dbg,
                             hipStream_t s, const timing_hook *hk = nullptr);

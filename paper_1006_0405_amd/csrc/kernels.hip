@@ -21,6 +21,7 @@
 #include <stdint.h>
 
 #include "fft8.hpp"
+#include "mr32.hpp"
 #include "internal.hpp"
 
 namespace ssa {
@@ -225,8 +226,9 @@ __device__ __forceinline__ ci separated_product(const ci &Z, const ci &W) {
 
 template <bool WAVE>
 __device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, int mode, int pack,
-                                           const twtab &T, double *dbg, double2 *h,
-                                           cert_shared &sh, uint32_t *sh_waves) {
+                                           int fp32, int hooks, int rerun, const twtab &T,
+                                           double *dbg, double2 *h, cert_shared &sh,
+                                           uint32_t *sh_waves) {
   const int M8 = 1 << (log_n - 3);
   const uint32_t mask = (1u << log_n) - 1u;
   const int j = threadIdx.x;
@@ -239,7 +241,21 @@ __device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, 
       const double db = static_cast<double>(digit(tk.b, tk.ndb, i, bits));
       va[r] = ci{-da, da, -db, db};
     }
-    fft8_group<WAVE>(va, j, log_n, h, 1, T);
+    if (fp32) {  // forward transform in FP32 discs, then back to double rectangles
+      mr w[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+        w[r] = mr{static_cast<float>(va[r].rh), static_cast<float>(va[r].ih), 0.0f};
+      mr_fft8_group<WAVE>(w, j, log_n, reinterpret_cast<float4 *>(h), T);
+      const float extra = (hooks & HOOK_FORCE_FP32_FAIL) ? 1.0e9f : 0.0f;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        w[r].r += extra;
+        va[r] = mr_to_ci(w[r]);
+      }
+    } else {
+      fft8_group<WAVE>(va, j, log_n, h, 1, T);
+    }
     // partners Z_{-k}: real halves, then imaginary halves
     double2 pr[8];
     xsync<WAVE>();
@@ -266,8 +282,26 @@ __device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, 
       va[r] = ci_thin_real(static_cast<double>(digit(tk.a, tk.nda, i, bits)));
       vb[r] = ci_thin_real(static_cast<double>(digit(tk.b, tk.ndb, i, bits)));
     }
-    fft8_group<WAVE>(va, j, log_n, h, 1, T);
-    fft8_group<WAVE>(vb, j, log_n, h, 1, T);
+    if (fp32) {
+      const float extra = (hooks & HOOK_FORCE_FP32_FAIL) ? 1.0e9f : 0.0f;
+      mr w[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) w[r] = mr{static_cast<float>(va[r].rh), 0.0f, 0.0f};
+      mr_fft8_group<WAVE>(w, j, log_n, reinterpret_cast<float4 *>(h), T);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        w[r].r += extra;
+        va[r] = mr_to_ci(w[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) w[r] = mr{static_cast<float>(vb[r].rh), 0.0f, 0.0f};
+      mr_fft8_group<WAVE>(w, j, log_n, reinterpret_cast<float4 *>(h), T);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) vb[r] = mr_to_ci(w[r]);
+    } else {
+      fft8_group<WAVE>(va, j, log_n, h, 1, T);
+      fft8_group<WAVE>(vb, j, log_n, h, 1, T);
+    }
 #pragma unroll
     for (int r = 0; r < 8; ++r) va[r] = ci_conj(ci_mul(va[r], vb[r]));
   }
@@ -315,23 +349,33 @@ __device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, 
     st->internal = sh.internal;
     st->carry_err = 0u;
     st->ticket = 0u;
+    st->fallback = (rerun && tk.fp32 != 0u) ? 1u : 0u;
+    st->fp32 = tk.fp32;
   }
 }
 
+// One product per workgroup.  fp32: first attempt with FP32 forward
+// transforms (every task of the launch is marked for it); rerun: the FP64
+// launch that follows such an attempt over the whole length class, where the
+// marked products that the attempt certified return at once.  The decision is
+// read from the statistics on the device, so a captured launch sequence holds
+// the fallback unconditionally.
 __global__ __launch_bounds__(512) void k_small(const task *tasks, int log_n, int bits, int mode,
-                                               int pack, twtab T, double *dbg) {
+                                               int pack, int fp32, int rerun, int hooks, twtab T,
+                                               double *dbg) {
   extern __shared__ double2 hbuf[];
   __shared__ cert_shared sh;
   __shared__ uint32_t sh_waves[8];
   const uint32_t z = enter_round_up();
   const task tk = after_mode(tasks, z)[blockIdx.x];
   T.tab = after_mode(T.tab, z);
+  if (rerun && tk.fp32 != 0u && tk.st->too_wide == 0u && tk.st->internal == 0u) return;
   if (threadIdx.x == 0) sh = cert_shared{0ull, 0ull, 0u, 0u};
   __syncthreads();
   if (log_n <= 9)
-    small_body<true>(tk, log_n, bits, mode, pack, T, dbg, hbuf, sh, sh_waves);
+    small_body<true>(tk, log_n, bits, mode, pack, fp32, hooks, rerun, T, dbg, hbuf, sh, sh_waves);
   else
-    small_body<false>(tk, log_n, bits, mode, pack, T, dbg, hbuf, sh, sh_waves);
+    small_body<false>(tk, log_n, bits, mode, pack, fp32, hooks, rerun, T, dbg, hbuf, sh, sh_waves);
 }
 
 // ---------------------------------------------------------------------------
@@ -360,6 +404,8 @@ __device__ __forceinline__ void reset_product_state(const task &tk) {
     tk.st->internal = 0u;
     tk.st->carry_err = 0u;
     tk.st->ticket = 0u;
+    tk.st->fallback = 0u;
+    tk.st->fp32 = 0u;
   }
   for (uint32_t t = threadIdx.x; t < tk.ntiles; t += blockDim.x) tk.tiles[t * TILE_WORD_STRIDE] = 0u;
 }
@@ -720,13 +766,13 @@ static inline void mark(const timing_hook *hk, int kind, int phase) {
 }
 
 hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bits, int cert_mode,
-                        int pack, const twtab_host &tw, double *dbg, hipStream_t s,
-                        const timing_hook *hk) {
+                        int pack, int fp32, int rerun, int hooks, const twtab_host &tw,
+                        double *dbg, hipStream_t s, const timing_hook *hk) {
   const int threads = 1 << (log_n - 3);
   const size_t lds = sizeof(double2) * lpad_size(size_t(1) << log_n);
   mark(hk, KIND_SMALL, 0);
   hipLaunchKernelGGL(k_small, dim3(ntasks), dim3(threads), lds, s, d_tasks, log_n, digit_bits,
-                     cert_mode, pack, to_dev(tw), dbg);
+                     cert_mode, pack, fp32, rerun, hooks, to_dev(tw), dbg);
   mark(hk, KIND_SMALL, 1);
   return hipGetLastError();
 }

@@ -1,0 +1,184 @@
+"""GPU tests of the FP32 first attempt with per-product FP64 re-run.
+
+An SSA_FP32_FALLBACK plan runs the forward transform of small products in FP32
+midpoint-radius discs (circular containment sets, paper section 4) and
+re-runs on the device, in FP64, every product that the attempt could not
+certify.  Whatever the path, a returned product must be the exact integer
+product (bit-exact against CPython's integers and the oracle); the statistics
+say which products needed the re-run.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1006_0405_amd import binding
+from paper_1006_0405_amd.workloads import all_ff, batch, pair
+from pins import exact_convolution, int_product, nibbles
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+SIZES = [(1, 1), (1, 2), (3, 5), (17, 33), (64, 65), (100, 100), (127, 2), (200, 57),
+         (255, 256), (300, 300), (511, 512), (1000, 1), (1023, 1025), (2048, 2048)]
+
+
+@pytest.mark.parametrize("separate", [False, True], ids=["packed", "separate"])
+@pytest.mark.parametrize("digit_bits", [8, 4])
+def test_fp32_attempt_products_exact(digit_bits, separate):
+    plan = binding.Plan(2048, 2048, digit_bits=digit_bits, separate_transforms=separate,
+                        precision="fp32_fallback")
+    plan.set_fp32_policy(4096)  # attempt FP32 on every single-workgroup product
+    used = []
+    for s, (na, nb) in enumerate(SIZES):
+        if digit_bits == 4 and na + nb > 2049:
+            continue
+        a, b = pair(700 + s, na, nb)
+        st, out = plan.mul(a, b)
+        assert st == binding.SSA_OK, (na, nb, binding.STATUS_NAMES.get(st, st))
+        assert np.array_equal(_np(out), int_product(a, b)), (na, nb)
+        assert plan.stats()["fp32_attempt"] == 1
+        used.append((na, nb, plan.stats()["fallback"]))
+    print("fallback per size:", used)
+    # the smallest products certify in FP32 without the re-run
+    limit = 8 if digit_bits == 8 else 130
+    assert all(f == 0 for na, nb, f in used if na + nb <= limit), used
+    plan.close()
+
+
+@pytest.mark.parametrize("na,nb,digit_bits", [(2, 1, 8), (40, 40, 4), (64, 20, 4),
+                                              (16, 100, 4)])
+def test_fp32_enclosures_contain_exact_coefficients(na, nb, digit_bits):
+    a, b = pair(na * 11 + nb, na, nb)
+    plan = binding.Plan(na, nb, digit_bits=digit_bits, precision="fp32_fallback")
+    plan.set_fp32_policy(4096)
+    st, out, enc = plan.debug_enclosures(a, b)
+    assert st == binding.SSA_OK
+    assert plan.stats()["fallback"] == 0  # the enclosures are the FP32 attempt's
+    enc = _np(enc)
+    assert np.array_equal(_np(out), int_product(a, b))
+    c = exact_convolution(a, b) if digit_bits == 8 else exact_convolution(nibbles(a), nibbles(b))
+    L = len(c)
+    assert np.all(enc[:L, 0] <= c) and np.all(c <= enc[:L, 1])
+    assert np.all(enc[:, 2] <= 0) and np.all(enc[:, 3] >= 0)
+    assert np.all(enc[L:, 0] <= 0) and np.all(enc[L:, 1] >= 0)
+    # FP32 discs are visibly wider than the FP64 rectangles: the attempt ran
+    r32 = plan.stats()["max_radius"]
+    plan64 = binding.Plan(na, nb, digit_bits=digit_bits)
+    st64, out64 = plan64.mul(a, b)
+    r64 = plan64.stats()["max_radius"]
+    assert st64 == binding.SSA_OK and np.array_equal(_np(out64), _np(out))
+    print("max radius FP32 attempt %.3e, FP64 %.3e" % (r32, r64))
+    assert r32 > 100 * r64
+    plan.close()
+    plan64.close()
+
+
+def test_forced_fallback_reruns_every_product_in_fp64():
+    plan = binding.Plan(2048, 2048, precision="fp32_fallback")
+    plan.set_fp32_policy(4096, force_fail=True)
+    for s, (na, nb) in enumerate(SIZES):
+        a, b = pair(900 + s, na, nb)
+        st, out = plan.mul(a, b)
+        assert st == binding.SSA_OK
+        assert np.array_equal(_np(out), int_product(a, b))
+        assert plan.stats()["fallback"] == 1
+    a = all_ff(2048)
+    st, out = plan.mul(a, a)
+    assert st == binding.SSA_OK and np.array_equal(_np(out), int_product(a, a))
+    plan.close()
+
+
+def test_fp32_policy_arguments():
+    plan64 = binding.Plan(100, 100)
+    with pytest.raises(binding.SsaError):
+        plan64.set_fp32_policy(10)
+    plan64.close()
+    plan = binding.Plan(100, 100, precision="fp32_fallback")
+    for bad in (-1, 4097, 1 << 20):
+        with pytest.raises(binding.SsaError):
+            plan.set_fp32_policy(bad)
+    plan.set_fp32_policy(0)  # attempt disabled: plain FP64
+    a, b = pair(5, 100, 100)
+    st, out = plan.mul(a, b)
+    assert st == binding.SSA_OK and plan.stats()["fallback"] == 0
+    assert np.array_equal(_np(out), int_product(a, b))
+    with pytest.raises(binding.SsaError):
+        binding.Plan(100, 100, precision="fp16")
+    plan.close()
+
+
+def test_fp32_batch_base16_exact_and_reports_fallback():
+    """The uneven-length batch (log-uniform 64..16384 bytes) in base 16 with
+    the default length predictor: every product exact, the fallback rate
+    reported."""
+    A, B = batch(seed=3)
+    plan = binding.Plan(16384, 16384, digit_bits=4, precision="fp32_fallback")
+    bt = binding.Batch(plan, A, B)
+    for rep in range(2):  # graph replays: stale statistics must not leak
+        status = _np(bt.run())
+        assert np.all(status == binding.SSA_OK)
+    for i in range(len(A)):
+        assert np.array_equal(_np(bt.OUT[i]), int_product(A[i], B[i])), i
+    st = bt.stats()
+    n_fb = sum(s["fallback"] for s in st)
+    n_try = sum(s["fp32_attempt"] for s in st)
+    print("FP32 first attempt: %d of %d products attempted, %d re-run in FP64"
+          % (n_try, len(st), n_fb))
+    for (a, b), s in zip(zip(A, B), st):
+        assert s["fp32_attempt"] == int(2 * (len(a) + len(b)) - 1 <= 511)
+        assert s["fallback"] <= s["fp32_attempt"]
+    bt.close()
+    plan.close()
+
+
+def test_fp32_batch_mixed_marked_and_unmarked():
+    """Within one transform length some products take the FP32 attempt and
+    some do not; certified attempts, re-runs and direct FP64 products all come
+    out exact, on two graph replays."""
+    rng = np.random.default_rng(45)
+    A, B = [], []
+    for i in range(300):
+        na, nb = int(rng.integers(1, 250)), int(rng.integers(1, 250))
+        a, b = pair(30_000 + i, na, nb)
+        A.append(a)
+        B.append(b)
+    plan = binding.Plan(250, 250, digit_bits=4, precision="fp32_fallback")
+    plan.set_fp32_policy(400)
+    bt = binding.Batch(plan, A, B)
+    for rep in range(2):
+        status = _np(bt.run())
+        assert np.all(status == binding.SSA_OK)
+        for i in range(len(A)):
+            assert np.array_equal(_np(bt.OUT[i]), int_product(A[i], B[i])), i
+    st = bt.stats()
+    marked = [2 * (len(a) + len(b)) - 1 <= 400 for a, b in zip(A, B)]
+    assert [s["fp32_attempt"] for s in st] == [int(m) for m in marked]
+    assert all(s["fallback"] == 0 for s, m in zip(st, marked) if not m)
+    print("marked %d, re-run %d" % (sum(marked), sum(s["fallback"] for s in st)))
+    bt.close()
+    plan.close()
+
+
+def test_fp32_batch_forced_fallback_twice():
+    rng = np.random.default_rng(44)
+    A, B = [], []
+    for i in range(200):
+        na, nb = int(rng.integers(1, 1500)), int(rng.integers(1, 1500))
+        a, b = pair(20_000 + i, na, nb)
+        A.append(a)
+        B.append(b)
+    plan = binding.Plan(1500, 1500, precision="fp32_fallback")
+    plan.set_fp32_policy(4096, force_fail=True)
+    bt = binding.Batch(plan, A, B)
+    for rep in range(2):
+        status = _np(bt.run())
+        assert np.all(status == binding.SSA_OK)
+        for i in range(len(A)):
+            assert np.array_equal(_np(bt.OUT[i]), int_product(A[i], B[i])), i
+        assert all(s["fallback"] == 1 and s["fp32_attempt"] == 1 for s in bt.stats())
+    bt.close()
+    plan.close()
