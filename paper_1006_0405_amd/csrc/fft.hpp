@@ -61,9 +61,4 @@ struct twtab {
   double e;
 };
 
-__device__ __forceinline__ ci apply_tw(const ci &v, const twtab &T, uint32_t t) {
-  const double2 w = T.tab[t];
-  return ci_twiddle(v, w.x, w.y, T.e);
-}
-
 }  // namespace ssa

@@ -112,7 +112,7 @@ __device__ __forceinline__ void exchange8(ci v[8], int j, int M8, double2 *h, in
 // i lives at h[lpad(i) * is].  With WAVE the group must be exactly the lanes of (part
 // of) one wavefront; otherwise every thread of the workgroup must call this with
 // the same M.
-template <bool WAVE>
+template <bool WAVE, bool PF = false>
 __device__ __forceinline__ void fft8_group(ci v[8], int j, int logM, double2 *h, int is,
                                            const twtab &T) {
   const int M8 = 1 << (logM - 3);
@@ -120,6 +120,17 @@ __device__ __forceinline__ void fft8_group(ci v[8], int j, int logM, double2 *h,
   const double c8 = w8.x, e8 = T.e;                  // |1/sqrt 2 - c8| <= e
   int logNs = 0;
   const int first = logM % 3;
+  // PF: twiddles of the next radix-8 stage are loaded one stage ahead, so that
+  // their latency overlaps the current stage's arithmetic and exchange (at the
+  // cost of 28 more live registers); otherwise they are loaded where used.
+  double2 w[8];
+  const auto load_tw = [&](int lns) {
+    const int sh = T.log_ntab - (lns + 3);
+    const int k = j & ((1 << lns) - 1);
+#pragma unroll
+    for (int r = 1; r < 8; ++r) w[r] = T.tab[static_cast<uint32_t>(r * k) << sh];
+  };
+  if (PF && first != 0) load_tw(first);  // the first radix-8 stage has Ns = 2 or 4
   if (first == 1) {
     // radix 2 (Ns = 1): this thread acts for positions jv = j + t M/8, t < 4,
     // pairs (x[jv], x[jv + M/2]) = (v_t, v_{t+4}); results to y[2 jv], y[2 jv + 1].
@@ -152,13 +163,20 @@ __device__ __forceinline__ void fft8_group(ci v[8], int j, int logM, double2 *h,
   for (;;) {
     const int Ns = 1 << logNs;
     const int k = j & (Ns - 1);
+    if (!PF && logNs > 0) load_tw(logNs);
     if (logNs > 0) {
-      const int sh = T.log_ntab - (logNs + 3);
+      // omega_{8 Ns}^{r k} with k < Ns has angle below r pi / 4: for r <= 2 the
+      // root lies in the first quadrant, for r <= 4 in the upper half plane,
+      // and so do the stored points (rounded to nearest from the same side)
 #pragma unroll
-      for (int r = 1; r < 8; ++r) v[r] = apply_tw(v[r], T, static_cast<uint32_t>(r * k) << sh);
+      for (int r = 1; r < 8; ++r)
+        v[r] = r <= 2 ? ci_twiddle_q1(v[r], w[r].x, w[r].y, T.e)
+             : r <= 4 ? ci_twiddle_uh(v[r], w[r].x, w[r].y, T.e)
+                      : ci_twiddle(v[r], w[r].x, w[r].y, T.e);
     }
     radix8(v, c8, e8);
     if (logNs + 3 == logM) break;  // last stage: X[j + q M/8] = v[q]
+    if (PF) load_tw(logNs + 3);
     const int base = ((j - k) << 3) + k;
     exchange8<WAVE>(v, j, M8, h, is, [&](int q) { return base + q * Ns; });
     logNs += 3;

@@ -78,6 +78,38 @@ __device__ __forceinline__ double ru_fma(double a, double b, double c) {
   asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
   return r;
 }
+// RU(a - b), RU(-a * b + c), RU(a * b - c), RU(a * |b| + c), RU(|a| + b):
+// negations and absolute values are source modifiers, exact.
+__device__ __forceinline__ double ru_sub(double a, double b) {
+  double r;
+  asm("v_add_f64 %0, %1, -%2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double ru_nfma(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, -%1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ double ru_fms(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, -%3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ double ru_fma_ab(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, |%2|, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ double ru_mul_ab(double a, double b) {
+  double r;
+  asm("v_mul_f64 %0, %1, |%2|" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double ru_add_aa(double a, double b) {
+  double r;
+  asm("v_add_f64 %0, |%1|, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
 // Operations that do not round (exact in any mode).
 __device__ __forceinline__ double dmax(double a, double b) {
   double r;
@@ -142,23 +174,77 @@ __device__ __forceinline__ ci ci_twiddle(const ci &z, double c, double s, double
   return r;
 }
 
-// The product of two stored roots w1 = (c1, s1), w2 = (c2, s2) (each within e
-// of the true root componentwise) as a point (c, s) with its own bound:
-// the exact product of the stored points lies in [-re_n, re_h] x [-im_n, im_h]
-// (bounds rounded up), and the true roots' product differs from it by at most
-// e (|c1| + |s1| + |c2| + |s2|) + 2 e^2 per component.
-struct twpoint {
-  double c, s, e;
+// Known-sign forms of ci_twiddle, for roots whose stored point is known to lie
+// in the closed first quadrant (c >= 0, s >= 0) or upper half plane (s >= 0):
+// the terms with the zero half of the sign split are dropped.
+__device__ __forceinline__ ci ci_twiddle_q1(const ci &z, double c, double s, double e) {
+  const double mx = dmax(z.rn, z.rh), my = dmax(z.in, z.ih);
+  const double E = ru_mul(e, ru_add(mx, my));
+  ci r;
+  r.rh = ru_fma(c, z.rh, ru_fma(s, z.in, E));
+  r.rn = ru_fma(c, z.rn, ru_fma(s, z.ih, E));
+  r.ih = ru_fma(s, z.rh, ru_fma(c, z.ih, E));
+  r.in = ru_fma(s, z.rn, ru_fma(c, z.in, E));
+  return r;
+}
+__device__ __forceinline__ ci ci_twiddle_uh(const ci &z, double c, double s, double e) {
+  const double cp = dmax(c, 0.0), cn = dmax(-c, 0.0);
+  const double mx = dmax(z.rn, z.rh), my = dmax(z.in, z.ih);
+  const double E = ru_mul(e, ru_add(mx, my));
+  ci r;
+  r.rh = ru_fma(cp, z.rh, ru_fma(cn, z.rn, ru_fma(s, z.in, E)));
+  r.rn = ru_fma(cp, z.rn, ru_fma(cn, z.rh, ru_fma(s, z.ih, E)));
+  r.ih = ru_fma(s, z.rh, ru_fma(cp, z.ih, ru_fma(cn, z.in, E)));
+  r.in = ru_fma(s, z.rn, ru_fma(cp, z.in, ru_fma(cn, z.ih, E)));
+  return r;
+}
+
+// Product of two stored roots as a point, with a bound valid for every pair:
+// each computed component is within 2^-51 of the exact product of the stored
+// points (two roundings of at most one ulp of a value of magnitude <= 1 + e),
+// which is within e (|c1| + |s1| + |c2| + |s2|) + 2 e^2 <= 2 sqrt(2) e + 2 e^2
+// of the true root; ep = pass_tw_bound(e) = 2^-50 + 3 e (rounded up) covers
+// both for any e < 0.08.
+__device__ __forceinline__ double pass_tw_bound(double e) {
+  return ru_fma(3.0, e, 0x1p-50);
+}
+__device__ __forceinline__ double2 tw_point_product(double2 w1, double2 w2) {
+  return make_double2(ru_fma(w1.x, w2.x, ru_nmul(w1.y, w2.y)), ru_fma(w1.x, w2.y, ru_mul(w1.y, w2.x)));
+}
+
+// Midpoint-radius form of the rectangular product (used for the pointwise
+// products): an interval [-n, h] scaled by s (s = 1 or 1/2, exact) as a
+// midpoint m and a radius r >= max(s h - m, m + s n), so m +- r encloses it
+// whatever rounding m carries.
+struct mrad {
+  double m, r;
 };
-__device__ __forceinline__ twpoint tw_product(double2 w1, double2 w2, double e) {
-  const double re_h = ru_fma(w1.x, w2.x, ru_nmul(w1.y, w2.y));
-  const double re_n = ru_fma(-w1.x, w2.x, ru_mul(w1.y, w2.y));
-  const double im_h = ru_fma(w1.x, w2.y, ru_mul(w1.y, w2.x));
-  const double im_n = ru_fma(-w1.x, w2.y, ru_nmul(w1.y, w2.x));
-  const double l1 = ru_add(ru_add(dabs(w1.x), dabs(w1.y)), ru_add(dabs(w2.x), dabs(w2.y)));
-  const double E2 = ru_fma(e, l1, ru_mul(ru_add(e, e), e));
-  const double ec = ru_add(ru_add(re_h, re_n), E2), es = ru_add(ru_add(im_h, im_n), E2);
-  return twpoint{re_h, im_h, dmax(ec, es)};
+__device__ __forceinline__ mrad to_mrad(double n, double h, double s) {
+  const double m = ru_mul(0.5 * s, ru_sub(h, n));
+  return mrad{m, dmax(ru_fms(s, h, m), ru_fma(s, n, m))};
+}
+// (ar + i ai)(br + i bi) with every part a midpoint-radius interval:
+//   Re = ar br - ai bi + d_re,  Im = ar bi + ai br + d_im,
+//   |d_re| <= (|ar| + rar) rbr + rar |br| + (|ai| + rai) rbi + rai |bi|,
+//   |d_im| <= (|ar| + rar) rbi + rar |bi| + (|ai| + rai) rbr + rai |br|
+// (from (a + x)(b + y) - a b = a y + x b + x y); the midpoint products are
+// bounded above and below by fused chains rounded up.  The result encloses the
+// exact set of products of the paper's section 2.5, about 40 FP64 operations
+// instead of 60 for the four-end-point form.
+__device__ __forceinline__ ci ci_mul_mrad(mrad ar, mrad ai, mrad br, mrad bi) {
+  const double t1 = ru_add_aa(ar.m, ar.r), t2 = ru_add_aa(ai.m, ai.r);
+  const double dre = ru_fma(t1, br.r, ru_fma_ab(ar.r, br.m, ru_fma(t2, bi.r, ru_mul_ab(ai.r, bi.m))));
+  const double dim = ru_fma(t1, bi.r, ru_fma_ab(ar.r, bi.m, ru_fma(t2, br.r, ru_mul_ab(ai.r, br.m))));
+  ci o;
+  o.rh = ru_add(ru_fma(ar.m, br.m, ru_nmul(ai.m, bi.m)), dre);
+  o.rn = ru_add(ru_nfma(ar.m, br.m, ru_mul(ai.m, bi.m)), dre);
+  o.ih = ru_add(ru_fma(ar.m, bi.m, ru_mul(ai.m, br.m)), dim);
+  o.in = ru_add(ru_nfma(ar.m, bi.m, ru_nmul(ai.m, br.m)), dim);
+  return o;
+}
+__device__ __forceinline__ ci ci_mul_fast(const ci &a, const ci &b) {
+  return ci_mul_mrad(to_mrad(a.rn, a.rh, 1.0), to_mrad(a.in, a.ih, 1.0), to_mrad(b.rn, b.rh, 1.0),
+                     to_mrad(b.in, b.ih, 1.0));
 }
 
 // Real interval product (paper section 2.5, four end-point products): with

@@ -214,9 +214,10 @@ __device__ __forceinline__ void carry_block(F C, long long p0, uint32_t nout, ui
 // multiplication by -i and by 1/2 are exact, so this is as rigorous as the
 // interval sum, difference and product it uses.
 __device__ __forceinline__ ci separated_product(const ci &Z, const ci &W) {
-  const ci A = ci_scale(ci_add(Z, W), 0.5);
-  const ci B = ci_scale(ci_mul_negi(ci_sub(Z, W)), 0.5);
-  return ci_mul(A, B);
+  const ci S = ci_add(Z, W), D = ci_sub(Z, W);
+  // A = S / 2;  B = -i D / 2, so Re B = Im D / 2 and Im B = -Re D / 2
+  return ci_mul_mrad(to_mrad(S.rn, S.rh, 0.5), to_mrad(S.in, S.ih, 0.5),
+                     to_mrad(D.in, D.ih, 0.5), to_mrad(D.rh, D.rn, 0.5));
 }
 
 // ---------------------------------------------------------------------------
@@ -303,7 +304,7 @@ __device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, 
       fft8_group<WAVE>(vb, j, log_n, h, 1, T);
     }
 #pragma unroll
-    for (int r = 0; r < 8; ++r) va[r] = ci_conj(ci_mul(va[r], vb[r]));
+    for (int r = 0; r < 8; ++r) va[r] = ci_conj(ci_mul_fast(va[r], vb[r]));
   }
   fft8_group<WAVE>(va, j, log_n, h, 1, T);
   const double scale = ldexp(1.0, -log_n);
@@ -384,16 +385,18 @@ __global__ __launch_bounds__(512) void k_small(const task *tasks, int log_n, int
 // Inter-pass twiddle omega_N^t, t = (a * b) mod N, as the product of two table
 // entries omega_N^{t_hi} omega_N^{t_lo} (t_hi a multiple of 2^h, t_lo < 2^h):
 // the two factors come from 2^(log_n - h) and 2^h entries of the table, which
-// stay cache-resident, instead of one scattered read over all N entries.
+// stay cache-resident, instead of one scattered read over all N entries.  The
+// product's error has one bound for every pair (pass_tw_bound).
 __device__ __forceinline__ ci apply_pass_tw(const ci &v, const twtab &T, uint32_t a, uint32_t b,
                                             int log_n) {
   const uint32_t t = (a * b) & ((1u << log_n) - 1u);
   const int h = (log_n + 1) >> 1;
   const int sh = T.log_ntab - log_n;
   const uint32_t thi = (t >> h) << h, tlo = t & ((1u << h) - 1u);
-  const twpoint w = tw_product(T.tab[thi << sh], T.tab[tlo << sh], T.e);
-  return ci_twiddle(v, w.c, w.s, w.e);
+  const double2 w = tw_point_product(T.tab[thi << sh], T.tab[tlo << sh]);
+  return ci_twiddle(v, w.x, w.y, pass_tw_bound(T.e));
 }
+
 
 // Statistics and carry-scan state of a product are reset by its first pass.
 __device__ __forceinline__ void reset_product_state(const task &tk) {
@@ -468,7 +471,7 @@ __device__ __forceinline__ void row_body(const task &tk, int log_n1, int log_n2,
   fft8_group<WAVE>(va, j, log_n2, hg, 1, T);
   fft8_group<WAVE>(vb, j, log_n2, hg, 1, T);
 #pragma unroll
-  for (int r = 0; r < 8; ++r) va[r] = ci_conj(ci_mul(va[r], vb[r]));
+  for (int r = 0; r < 8; ++r) va[r] = ci_conj(ci_mul_fast(va[r], vb[r]));
   fft8_group<WAVE>(va, j, log_n2, hg, 1, T);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
@@ -516,7 +519,7 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int lo
   ci v[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) v[r] = gld(tk.ya, row + j + r * M8);
-  fft8_group<WAVE>(v, j, log_n2, hown, 1, T);
+  fft8_group<WAVE, true>(v, j, log_n2, hown, 1, T);
   // partner values, real halves then imaginary halves (workgroup barriers:
   // the partner row may be another wavefront)
   uint32_t src[8];
@@ -543,7 +546,7 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int lo
     v[r] = ci_conj(separated_product(v[r], W));
   }
   __syncthreads();  // the partner has read this row's buffer
-  fft8_group<WAVE>(v, j, log_n2, hown, 1, T);
+  fft8_group<WAVE, true>(v, j, log_n2, hown, 1, T);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const uint32_t n2 = j + q * M8;
