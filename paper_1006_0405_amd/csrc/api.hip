@@ -292,7 +292,7 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
     p->cfg[l] = default_cfg(l, o.separate_transforms ? 0 : 1);
   const size_t N = size_t(1) << log_nmax;
   const size_t ntiles = (max_na + max_nb + CARRY_TILE - 1) / CARRY_TILE;
-  bool ok = hip_ok(hipMalloc(&p->tab, sizeof(double2) << p->log_ntab)) &&
+  bool ok = hip_ok(hipMalloc(&p->tab, sizeof(double2) << (p->log_ntab + 1))) &&  // level tables
             hip_ok(hipMalloc(&p->ebits, sizeof(unsigned long long))) &&
             hip_ok(hipMalloc(&p->roots, twiddle_roots_bytes())) &&
             hip_ok(hipMalloc(&p->c, sizeof(unsigned long long) * N)) &&
@@ -311,7 +311,8 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
   // certified twiddles: the bound e is read back once and passed by value
   unsigned long long eb = 0;
   ok = hip_ok(hipMemcpyAsync(p->ebits, &eb, sizeof(eb), hipMemcpyHostToDevice, p->stream)) &&
-       hip_ok(make_twiddles(p->log_ntab, p->tab, p->ebits, p->roots, p->stream)) &&
+       hip_ok(make_twiddles(p->log_ntab, p->tab + N, p->ebits, p->roots, p->stream)) &&
+       hip_ok(make_level_tables(p->log_ntab, p->tab, p->stream)) &&
        hip_ok(hipMemcpyAsync(&eb, p->ebits, sizeof(eb), hipMemcpyDeviceToHost, p->stream)) &&
        hip_ok(hipStreamSynchronize(p->stream));
   if (!ok) {
@@ -358,7 +359,8 @@ ssa_status ssa_get_stats(const ssa_plan *plan, ssa_stats *stats_host) {
 ssa_status ssa_twiddle_table(const ssa_plan *plan, double *tab_dev, double *e_host,
                              int *log_ntab_host) {
   if (!plan || !tab_dev || !e_host || !log_ntab_host) return SSA_INVALID_ARGUMENT;
-  if (!hip_ok(hipMemcpyAsync(tab_dev, plan->tab, sizeof(double2) << plan->log_ntab,
+  if (!hip_ok(hipMemcpyAsync(tab_dev, plan->tab + (size_t(1) << plan->log_ntab),
+                             sizeof(double2) << plan->log_ntab,
                              hipMemcpyDeviceToDevice, plan->stream)) ||
       !hip_ok(hipStreamSynchronize(plan->stream)))
     return SSA_DEVICE_ERROR;

@@ -53,12 +53,17 @@ __device__ __forceinline__ void radix4(ci v[4]) {
   v[3] = ci_sub(b, id);
 }
 
-// Twiddle table: omega_{Ntab}^t for 0 <= t < Ntab as point values (c, s) with
-// a common absolute error bound e on each component.
+// Twiddle tables by level: tab[2^l + u] = omega_{2^l}^u (l <= log_ntab,
+// u < 2^l) as point values (c, s) with a common absolute error bound e on each
+// component.  The roots of one order are contiguous, so the twiddles of a
+// length-2^l transform stay within a few cache lines.
 struct twtab {
   const double2 *tab;
   int log_ntab;
   double e;
 };
+__device__ __forceinline__ double2 root(const twtab &T, int l, uint32_t u) {
+  return T.tab[(1u << l) + u];
+}
 
 }  // namespace ssa

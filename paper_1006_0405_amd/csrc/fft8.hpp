@@ -116,7 +116,7 @@ template <bool WAVE, bool PF = false>
 __device__ __forceinline__ void fft8_group(ci v[8], int j, int logM, double2 *h, int is,
                                            const twtab &T) {
   const int M8 = 1 << (logM - 3);
-  const double2 w8 = T.tab[1u << (T.log_ntab - 3)];  // omega_8 from the table
+  const double2 w8 = root(T, 3, 1);  // omega_8 from the table
   const double c8 = w8.x, e8 = T.e;                  // |1/sqrt 2 - c8| <= e
   int logNs = 0;
   const int first = logM % 3;
@@ -125,10 +125,9 @@ __device__ __forceinline__ void fft8_group(ci v[8], int j, int logM, double2 *h,
   // cost of 28 more live registers); otherwise they are loaded where used.
   double2 w[8];
   const auto load_tw = [&](int lns) {
-    const int sh = T.log_ntab - (lns + 3);
     const int k = j & ((1 << lns) - 1);
 #pragma unroll
-    for (int r = 1; r < 8; ++r) w[r] = T.tab[static_cast<uint32_t>(r * k) << sh];
+    for (int r = 1; r < 8; ++r) w[r] = root(T, lns + 3, static_cast<uint32_t>(r * k));
   };
   if (PF && first != 0) load_tw(first);  // the first radix-8 stage has Ns = 2 or 4
   if (first == 1) {

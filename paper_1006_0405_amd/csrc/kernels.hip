@@ -383,17 +383,15 @@ __global__ __launch_bounds__(512) void k_small(const task *tasks, int log_n, int
 // Multi-pass kernels.
 
 // Inter-pass twiddle omega_N^t, t = (a * b) mod N, as the product of two table
-// entries omega_N^{t_hi} omega_N^{t_lo} (t_hi a multiple of 2^h, t_lo < 2^h):
-// the two factors come from 2^(log_n - h) and 2^h entries of the table, which
-// stay cache-resident, instead of one scattered read over all N entries.  The
-// product's error has one bound for every pair (pass_tw_bound).
+// entries: the two factors come from 2^(log_n - h) and 2^h contiguous entries,
+// which stay cache-resident, instead of one scattered read over all N entries.
+// The product's error has one bound for every pair (pass_tw_bound).
 __device__ __forceinline__ ci apply_pass_tw(const ci &v, const twtab &T, uint32_t a, uint32_t b,
                                             int log_n) {
   const uint32_t t = (a * b) & ((1u << log_n) - 1u);
   const int h = (log_n + 1) >> 1;
-  const int sh = T.log_ntab - log_n;
-  const uint32_t thi = (t >> h) << h, tlo = t & ((1u << h) - 1u);
-  const double2 w = tw_point_product(T.tab[thi << sh], T.tab[tlo << sh]);
+  // omega_N^t = omega_{N / 2^h}^{t >> h} * omega_N^{t mod 2^h}
+  const double2 w = tw_point_product(root(T, log_n - h, t >> h), root(T, log_n, t & ((1u << h) - 1u)));
   return ci_twiddle(v, w.x, w.y, pass_tw_bound(T.e));
 }
 

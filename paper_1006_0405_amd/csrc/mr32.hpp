@@ -116,7 +116,7 @@ __device__ __forceinline__ void mr_exchange8(mr v[8], int j, int M8, float4 *h, 
 template <bool WAVE>
 __device__ __forceinline__ void mr_fft8_group(mr v[8], int j, int logM, float4 *h, const twtab &T) {
   const int M8 = 1 << (logM - 3);
-  const float c8 = static_cast<float>(T.tab[1u << (T.log_ntab - 3)].x);
+  const float c8 = static_cast<float>(root(T, 3, 1).x);
   int logNs = 0;
   const int first = logM % 3;
   if (first == 1) {
@@ -148,9 +148,8 @@ __device__ __forceinline__ void mr_fft8_group(mr v[8], int j, int logM, float4 *
     const int Ns = 1 << logNs;
     const int k = j & (Ns - 1);
     if (logNs > 0) {
-      const int sh = T.log_ntab - (logNs + 3);
 #pragma unroll
-      for (int r = 1; r < 8; ++r) v[r] = mr_tw_tab(v[r], T.tab[static_cast<uint32_t>(r * k) << sh]);
+      for (int r = 1; r < 8; ++r) v[r] = mr_tw_tab(v[r], root(T, logNs + 3, static_cast<uint32_t>(r * k)));
     }
     mr_radix8(v, c8);
     if (logNs + 3 == logM) break;

@@ -192,4 +192,23 @@ hipError_t make_twiddles(int K, double2 *tab, unsigned long long *ebits, void *r
 
 size_t twiddle_roots_bytes() { return sizeof(fc) * 64; }
 
+__global__ void k_levels(int K, double2 *lv) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (1u << K)) return;
+  if (i == 0) {
+    lv[0] = make_double2(1.0, 0.0);  // unused slot
+    return;
+  }
+  const int l = 31 - __builtin_clz(i);
+  const uint32_t u = i - (1u << l);
+  lv[i] = lv[(1u << K) + (u << (K - l))];
+}
+
+hipError_t make_level_tables(int K, double2 *lv, hipStream_t stream) {
+  const uint32_t n = 1u << K;
+  const uint32_t bs = 256;
+  hipLaunchKernelGGL(k_levels, dim3((n + bs - 1) / bs), dim3(bs), 0, stream, K, lv);
+  return hipGetLastError();
+}
+
 }  // namespace ssa
