@@ -30,11 +30,18 @@ namespace ssa {
 // Digits (section 2: little-endian base-b vectors); base 16 splits each byte
 // into (low nibble, high nibble).
 
-__device__ __forceinline__ uint32_t digit(const uint8_t *p, uint32_t nd, uint32_t i, int bits) {
-  if (i >= nd) return 0u;
-  if (bits == 8) return gload(p + i);
-  const uint32_t byte = gload(p + (i >> 1));
-  return (i & 1u) ? (byte >> 4) : (byte & 15u);
+// Digit i of an operand with nd >= 1 digits (0 past the end), in two steps so
+// that every load of a thread is issued before the first wait: load_digit
+// reads the byte holding digit i (clamped into the operand, no branch) and
+// digit_value extracts the digit and discards it past the end.
+__device__ __forceinline__ uint32_t load_digit(const uint8_t *p, uint32_t nd, uint32_t i, int bits) {
+  const uint32_t ic = i < nd ? i : nd - 1u;
+  return gload(p + (ic >> (bits == 4 ? 1 : 0)));
+}
+__device__ __forceinline__ double digit_value(uint32_t raw, uint32_t nd, uint32_t i, int bits) {
+  const uint32_t half = bits == 4 ? 1u : 0u;
+  const uint32_t x = (raw >> ((i & half) << 2)) & (half ? 15u : 255u);
+  return static_cast<double>(i < nd ? x : 0u);
 }
 
 // ---------------------------------------------------------------------------
@@ -234,12 +241,17 @@ __device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, 
   const uint32_t mask = (1u << log_n) - 1u;
   const int j = threadIdx.x;
   ci va[8];
+  uint32_t ra[8], rb[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    ra[r] = load_digit(tk.a, tk.nda, j + r * M8, bits);
+    rb[r] = load_digit(tk.b, tk.ndb, j + r * M8, bits);
+  }
   if (pack) {  // one transform of z = a + i b, then separation
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      const uint32_t i = j + r * M8;
-      const double da = static_cast<double>(digit(tk.a, tk.nda, i, bits));
-      const double db = static_cast<double>(digit(tk.b, tk.ndb, i, bits));
+      const double da = digit_value(ra[r], tk.nda, j + r * M8, bits);
+      const double db = digit_value(rb[r], tk.ndb, j + r * M8, bits);
       va[r] = ci{-da, da, -db, db};
     }
     if (fp32) {  // forward transform in FP32 discs, then back to double rectangles
@@ -279,9 +291,8 @@ __device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, 
     ci vb[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      const uint32_t i = j + r * M8;
-      va[r] = ci_thin_real(static_cast<double>(digit(tk.a, tk.nda, i, bits)));
-      vb[r] = ci_thin_real(static_cast<double>(digit(tk.b, tk.ndb, i, bits)));
+      va[r] = ci_thin_real(digit_value(ra[r], tk.nda, j + r * M8, bits));
+      vb[r] = ci_thin_real(digit_value(rb[r], tk.ndb, j + r * M8, bits));
     }
     if (fp32) {
       const float extra = (hooks & HOOK_FORCE_FP32_FAIL) ? 1.0e9f : 0.0f;
@@ -396,6 +407,12 @@ __device__ __forceinline__ ci apply_pass_tw(const ci &v, const twtab &T, uint32_
 }
 
 
+// Keeps the compiler from interleaving the final stores with the twiddle loads
+// before them: one counter tracks both loads and stores, so a load issued
+// after a store cannot be waited for without also waiting for that store, and
+// each interleaved pair would cost a full memory round trip.
+__device__ __forceinline__ void stores_after_loads() { __builtin_amdgcn_sched_barrier(0); }
+
 // Statistics and carry-scan state of a product are reset by its first pass.
 __device__ __forceinline__ void reset_product_state(const task &tk) {
   if (threadIdx.x == 0) {
@@ -425,28 +442,33 @@ __global__ __launch_bounds__(512) void k_col_fwd(const task *tasks, int log_n1, 
   const uint32_t n2 = blockIdx.x * C + c;
   const bool opb = blockIdx.y != 0;
   if (blockIdx.x == 0 && !opb) reset_product_state(tk);
+  uint32_t idx[8], ra[8], rb[8];
   const uint8_t *p = opb ? tk.b : tk.a;
   const uint32_t nd = opb ? tk.ndb : tk.nda;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    idx[r] = (static_cast<uint32_t>(j + r * M8) << log_n2) + n2;
+    ra[r] = load_digit(pack ? tk.a : p, pack ? tk.nda : nd, idx[r], bits);
+    if (pack) rb[r] = load_digit(tk.b, tk.ndb, idx[r], bits);
+  }
   ci v[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const uint32_t n1 = j + r * M8;
-    const uint32_t i = (n1 << log_n2) + n2;
     if (pack) {  // z = a + i b: both real operands in one complex transform
-      const double da = static_cast<double>(digit(tk.a, tk.nda, i, bits));
-      const double db = static_cast<double>(digit(tk.b, tk.ndb, i, bits));
+      const double da = digit_value(ra[r], tk.nda, idx[r], bits);
+      const double db = digit_value(rb[r], tk.ndb, idx[r], bits);
       v[r] = ci{-da, da, -db, db};
     } else {
-      v[r] = ci_thin_real(static_cast<double>(digit(p, nd, i, bits)));
+      v[r] = ci_thin_real(digit_value(ra[r], nd, idx[r], bits));
     }
   }
   fft8_group<false>(v, j, log_n1, hbuf + c, C, T);
   ci *Y = opb ? tk.yb : tk.ya;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const uint32_t k1 = j + q * M8;
-    gst(Y, (static_cast<size_t>(k1) << log_n2) + n2, apply_pass_tw(v[q], T, n2, k1, log_n));
-  }
+  for (int q = 0; q < 8; ++q) v[q] = apply_pass_tw(v[q], T, n2, j + q * M8, log_n);
+  stores_after_loads();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) gst(Y, (static_cast<size_t>(j + q * M8) << log_n2) + n2, v[q]);
 }
 
 // Rows (one transform per operand): R rows k1 per workgroup, N2/8 threads per
@@ -472,10 +494,10 @@ __device__ __forceinline__ void row_body(const task &tk, int log_n1, int log_n2,
   for (int r = 0; r < 8; ++r) va[r] = ci_conj(ci_mul_fast(va[r], vb[r]));
   fft8_group<WAVE>(va, j, log_n2, hg, 1, T);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const uint32_t n2 = j + q * M8;
-    gst(tk.ya, row + n2, ci_conj(apply_pass_tw(va[q], T, n2, k1, log_n)));
-  }
+  for (int q = 0; q < 8; ++q) va[q] = ci_conj(apply_pass_tw(va[q], T, j + q * M8, k1, log_n));
+  stores_after_loads();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) gst(tk.ya, row + j + q * M8, va[q]);
 }
 
 __global__ __launch_bounds__(512) void k_row(const task *tasks, int log_n1, int log_n2, int R,
@@ -546,10 +568,10 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int lo
   __syncthreads();  // the partner has read this row's buffer
   fft8_group<WAVE, true>(v, j, log_n2, hown, 1, T);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const uint32_t n2 = j + q * M8;
-    gst(tk.ya, row + n2, ci_conj(apply_pass_tw(v[q], T, n2, k1, log_n)));
-  }
+  for (int q = 0; q < 8; ++q) v[q] = ci_conj(apply_pass_tw(v[q], T, j + q * M8, k1, log_n));
+  stores_after_loads();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) gst(tk.ya, row + j + q * M8, v[q]);
 }
 
 __global__ __launch_bounds__(512) void k_row_pair(const task *tasks, int log_n1, int log_n2,
