@@ -392,6 +392,13 @@ __global__ __launch_bounds__(512) void k_small(const task *tasks, int log_n, int
 
 // ---------------------------------------------------------------------------
 // Multi-pass kernels.
+//
+// Pass order over the products of a launch alternates: the column passes and
+// the single-workgroup products take products in ascending order, the row pass
+// and the carry scan in descending order.  Each pass therefore starts on the
+// products whose data the previous pass wrote last, which are still held in
+// the last-level cache (256 MB Infinity Cache on MI355X) when a launch's
+// arrays are larger than it.
 
 // Inter-pass twiddle omega_N^t, t = (a * b) mod N, as the product of two table
 // entries: the two factors come from 2^(log_n - h) and 2^h contiguous entries,
@@ -504,7 +511,7 @@ __global__ __launch_bounds__(512) void k_row(const task *tasks, int log_n1, int 
                                              twtab T) {
   extern __shared__ double2 hbuf[];
   const uint32_t z = enter_round_up();
-  const task tk = after_mode(tasks, z)[blockIdx.y];
+  const task tk = after_mode(tasks, z)[gridDim.y - 1 - blockIdx.y];  // last written first
   T.tab = after_mode(T.tab, z);
   if (log_n2 <= 9)
     row_body<true>(tk, log_n1, log_n2, R, T, hbuf);
@@ -578,7 +585,7 @@ __global__ __launch_bounds__(512) void k_row_pair(const task *tasks, int log_n1,
                                                   int G, twtab T) {
   extern __shared__ double2 hbuf[];
   const uint32_t z = enter_round_up();
-  const task tk = after_mode(tasks, z)[blockIdx.y];
+  const task tk = after_mode(tasks, z)[gridDim.y - 1 - blockIdx.y];  // last written first
   T.tab = after_mode(T.tab, z);
   if (log_n2 <= 9)
     row_pair_body<true>(tk, log_n1, log_n2, G, T, hbuf);
@@ -688,7 +695,7 @@ __global__ __launch_bounds__(CARRY_THREADS) void k_carry(const task *tasks, int 
   __shared__ uint32_t sh_tile;
   __shared__ uint32_t sh_failed;
   __shared__ unsigned long long sC[CARRY_TILE + 8];
-  const task tk = tasks[blockIdx.y];
+  const task tk = tasks[gridDim.y - 1 - blockIdx.y];  // last written first
   if (blockIdx.x >= tk.ntiles) return;
   if (threadIdx.x == 0) {
     sh_tile = atomicAdd(&tk.st->ticket, 1u);
