@@ -86,40 +86,42 @@ __device__ __forceinline__ void hput(double2 *h, int idx, double x, double y) {
 }
 
 // Move the 8 values of this thread to positions wpos(q) and read back the
-// values at rpos(r) = j + r M/8, in two 16-byte rounds.
+// values at rpos(r) = j + r M/8, in two 16-byte rounds.  Element i of the
+// buffer lives at h[lpad(i) << lis].
 template <bool WAVE, class W>
-__device__ __forceinline__ void exchange8(ci v[8], int j, int M8, double2 *h, int is, W wpos) {
+__device__ __forceinline__ void exchange8(ci v[8], int j, int M8, double2 *h, int lis, W wpos) {
   double2 t[8];
   xsync<WAVE>();
 #pragma unroll
-  for (int q = 0; q < 8; ++q) hput(h, lpad(wpos(q)) * is, v[q].rn, v[q].rh);
+  for (int q = 0; q < 8; ++q) hput(h, lpad(wpos(q)) << lis, v[q].rn, v[q].rh);
   xsync<WAVE>();
 #pragma unroll
-  for (int r = 0; r < 8; ++r) t[r] = h[lpad(j + r * M8) * is];
+  for (int r = 0; r < 8; ++r) t[r] = h[lpad(j + r * M8) << lis];
   xsync<WAVE>();
 #pragma unroll
-  for (int q = 0; q < 8; ++q) hput(h, lpad(wpos(q)) * is, v[q].in, v[q].ih);
+  for (int q = 0; q < 8; ++q) hput(h, lpad(wpos(q)) << lis, v[q].in, v[q].ih);
   xsync<WAVE>();
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const double2 u = h[lpad(j + r * M8) * is];
+    const double2 u = h[lpad(j + r * M8) << lis];
     v[r] = ci{t[r].x, t[r].y, u.x, u.y};
   }
 }
 
-// Forward interval DFT of the group's M = 2^logM elements (logM >= 3).
-// `h` points at element 0 of this group's half-element exchange buffer; element
-// i lives at h[lpad(i) * is].  With WAVE the group must be exactly the lanes of (part
-// of) one wavefront; otherwise every thread of the workgroup must call this with
-// the same M.
-template <bool WAVE, bool PF = false>
-__device__ __forceinline__ void fft8_group(ci v[8], int j, int logM, double2 *h, int is,
-                                           const twtab &T) {
-  const int M8 = 1 << (logM - 3);
+// Forward interval DFT of the group's M = 2^LOGM elements (LOGM >= 3), a
+// compile-time length so that the stage sequence and every index is fixed
+// when the kernel is compiled.  `h` points at element 0 of this group's
+// half-element exchange buffer; element i lives at h[lpad(i) << lis].  With
+// WAVE the group must be exactly the lanes of (part of) one wavefront;
+// otherwise every thread of the workgroup must call this with the same M.
+template <int LOGM, bool WAVE, bool PF = false>
+__device__ __forceinline__ void fft8_group(ci v[8], int j, double2 *h, int lis, const twtab &T) {
+  static_assert(LOGM >= 3, "length-8 groups at least");
+  constexpr int M8 = 1 << (LOGM - 3);
+  constexpr int FIRST = LOGM % 3;           // radix-2 (1) or radix-4 (2) first stage, or none (0)
+  constexpr int NR8 = (LOGM - FIRST) / 3;   // radix-8 stages
   const double2 w8 = root(T, 3, 1);  // omega_8 from the table
-  const double c8 = w8.x, e8 = T.e;                  // |1/sqrt 2 - c8| <= e
-  int logNs = 0;
-  const int first = logM % 3;
+  const double c8 = w8.x, e8 = T.e;  // |1/sqrt 2 - c8| <= e
   // PF: twiddles of the next radix-8 stage are loaded one stage ahead, so that
   // their latency overlaps the current stage's arithmetic and exchange (at the
   // cost of 28 more live registers); otherwise they are loaded where used.
@@ -129,8 +131,8 @@ __device__ __forceinline__ void fft8_group(ci v[8], int j, int logM, double2 *h,
 #pragma unroll
     for (int r = 1; r < 8; ++r) w[r] = root(T, lns + 3, static_cast<uint32_t>(r * k));
   };
-  if (PF && first != 0) load_tw(first);  // the first radix-8 stage has Ns = 2 or 4
-  if (first == 1) {
+  if (PF && FIRST != 0) load_tw(FIRST);  // the first radix-8 stage has Ns = 2 or 4
+  if (FIRST == 1) {
     // radix 2 (Ns = 1): this thread acts for positions jv = j + t M/8, t < 4,
     // pairs (x[jv], x[jv + M/2]) = (v_t, v_{t+4}); results to y[2 jv], y[2 jv + 1].
     ci y[8];
@@ -139,11 +141,10 @@ __device__ __forceinline__ void fft8_group(ci v[8], int j, int logM, double2 *h,
       y[2 * t] = ci_add(v[t], v[t + 4]);
       y[2 * t + 1] = ci_sub(v[t], v[t + 4]);
     }
-    exchange8<WAVE>(y, j, M8, h, is, [&](int q) { return 2 * (j + (q >> 1) * M8) + (q & 1); });
+    exchange8<WAVE>(y, j, M8, h, lis, [&](int q) { return 2 * (j + (q >> 1) * M8) + (q & 1); });
 #pragma unroll
     for (int r = 0; r < 8; ++r) v[r] = y[r];
-    logNs = 1;
-  } else if (first == 2) {
+  } else if (FIRST == 2) {
     // radix 4 (Ns = 1): positions jv = j + t M/8, t < 2, elements
     // x[jv + s M/4] = v_{t + 2 s}; results to y[4 jv + q].
     ci y[8];
@@ -154,12 +155,13 @@ __device__ __forceinline__ void fft8_group(ci v[8], int j, int logM, double2 *h,
 #pragma unroll
       for (int q = 0; q < 4; ++q) y[4 * t + q] = u[q];
     }
-    exchange8<WAVE>(y, j, M8, h, is, [&](int q) { return 4 * (j + (q >> 2) * M8) + (q & 3); });
+    exchange8<WAVE>(y, j, M8, h, lis, [&](int q) { return 4 * (j + (q >> 2) * M8) + (q & 3); });
 #pragma unroll
     for (int r = 0; r < 8; ++r) v[r] = y[r];
-    logNs = 2;
   }
-  for (;;) {
+#pragma unroll
+  for (int st = 0; st < NR8; ++st) {
+    const int logNs = FIRST + 3 * st;
     const int Ns = 1 << logNs;
     const int k = j & (Ns - 1);
     if (!PF && logNs > 0) load_tw(logNs);
@@ -174,11 +176,10 @@ __device__ __forceinline__ void fft8_group(ci v[8], int j, int logM, double2 *h,
                       : ci_twiddle(v[r], w[r].x, w[r].y, T.e);
     }
     radix8(v, c8, e8);
-    if (logNs + 3 == logM) break;  // last stage: X[j + q M/8] = v[q]
+    if (st + 1 == NR8) break;  // last stage: X[j + q M/8] = v[q]
     if (PF) load_tw(logNs + 3);
     const int base = ((j - k) << 3) + k;
-    exchange8<WAVE>(v, j, M8, h, is, [&](int q) { return base + q * Ns; });
-    logNs += 3;
+    exchange8<WAVE>(v, j, M8, h, lis, [&](int q) { return base + q * Ns; });
   }
 }
 

@@ -232,13 +232,13 @@ __device__ __forceinline__ ci separated_product(const ci &Z, const ci &W) {
 // 2^9 <= N <= 2^12.  LDS: N half-elements (16 B) for the exchanges, reused for
 // the coefficients.
 
-template <bool WAVE>
-__device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, int mode, int pack,
+template <int LOG_N, bool WAVE>
+__device__ __forceinline__ void small_body(const task &tk, int bits, int mode, int pack,
                                            int fp32, int hooks, int rerun, const twtab &T,
                                            double *dbg, double2 *h, cert_shared &sh,
                                            uint32_t *sh_waves) {
-  const int M8 = 1 << (log_n - 3);
-  const uint32_t mask = (1u << log_n) - 1u;
+  constexpr int M8 = 1 << (LOG_N - 3);
+  constexpr uint32_t mask = (1u << LOG_N) - 1u;
   const int j = threadIdx.x;
   ci va[8];
   uint32_t ra[8], rb[8];
@@ -259,7 +259,7 @@ __device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, 
 #pragma unroll
       for (int r = 0; r < 8; ++r)
         w[r] = mr{static_cast<float>(va[r].rh), static_cast<float>(va[r].ih), 0.0f};
-      mr_fft8_group<WAVE>(w, j, log_n, reinterpret_cast<float4 *>(h), T);
+      mr_fft8_group<LOG_N, WAVE>(w, j, reinterpret_cast<float4 *>(h), T);
       const float extra = (hooks & HOOK_FORCE_FP32_FAIL) ? 1.0e9f : 0.0f;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
@@ -267,7 +267,7 @@ __device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, 
         va[r] = mr_to_ci(w[r]);
       }
     } else {
-      fft8_group<WAVE>(va, j, log_n, h, 1, T);
+      fft8_group<LOG_N, WAVE>(va, j, h, 0, T);
     }
     // partners Z_{-k}: real halves, then imaginary halves
     double2 pr[8];
@@ -299,7 +299,7 @@ __device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, 
       mr w[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) w[r] = mr{static_cast<float>(va[r].rh), 0.0f, 0.0f};
-      mr_fft8_group<WAVE>(w, j, log_n, reinterpret_cast<float4 *>(h), T);
+      mr_fft8_group<LOG_N, WAVE>(w, j, reinterpret_cast<float4 *>(h), T);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         w[r].r += extra;
@@ -307,18 +307,18 @@ __device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, 
       }
 #pragma unroll
       for (int r = 0; r < 8; ++r) w[r] = mr{static_cast<float>(vb[r].rh), 0.0f, 0.0f};
-      mr_fft8_group<WAVE>(w, j, log_n, reinterpret_cast<float4 *>(h), T);
+      mr_fft8_group<LOG_N, WAVE>(w, j, reinterpret_cast<float4 *>(h), T);
 #pragma unroll
       for (int r = 0; r < 8; ++r) vb[r] = mr_to_ci(w[r]);
     } else {
-      fft8_group<WAVE>(va, j, log_n, h, 1, T);
-      fft8_group<WAVE>(vb, j, log_n, h, 1, T);
+      fft8_group<LOG_N, WAVE>(va, j, h, 0, T);
+      fft8_group<LOG_N, WAVE>(vb, j, h, 0, T);
     }
 #pragma unroll
     for (int r = 0; r < 8; ++r) va[r] = ci_conj(ci_mul_fast(va[r], vb[r]));
   }
-  fft8_group<WAVE>(va, j, log_n, h, 1, T);
-  const double scale = ldexp(1.0, -log_n);
+  fft8_group<LOG_N, WAVE>(va, j, h, 0, T);
+  const double scale = ldexp(1.0, -LOG_N);
   cert_acc acc{0.0, 0u, 0u, 0u};
   unsigned long long cv[8];
 #pragma unroll
@@ -372,8 +372,9 @@ __device__ __forceinline__ void small_body(const task &tk, int log_n, int bits, 
 // marked products that the attempt certified return at once.  The decision is
 // read from the statistics on the device, so a captured launch sequence holds
 // the fallback unconditionally.
-__global__ __launch_bounds__(512) void k_small(const task *tasks, int log_n, int bits, int mode,
-                                               int pack, int fp32, int rerun, int hooks, twtab T,
+template <int LOG_N>
+__global__ __launch_bounds__(512) void k_small(const task *tasks, int bits, int mode, int pack,
+                                               int fp32, int rerun, int hooks, twtab T,
                                                double *dbg) {
   extern __shared__ double2 hbuf[];
   __shared__ cert_shared sh;
@@ -384,10 +385,8 @@ __global__ __launch_bounds__(512) void k_small(const task *tasks, int log_n, int
   if (rerun && tk.fp32 != 0u && tk.st->too_wide == 0u && tk.st->internal == 0u) return;
   if (threadIdx.x == 0) sh = cert_shared{0ull, 0ull, 0u, 0u};
   __syncthreads();
-  if (log_n <= 9)
-    small_body<true>(tk, log_n, bits, mode, pack, fp32, hooks, rerun, T, dbg, hbuf, sh, sh_waves);
-  else
-    small_body<false>(tk, log_n, bits, mode, pack, fp32, hooks, rerun, T, dbg, hbuf, sh, sh_waves);
+  small_body<LOG_N, (LOG_N <= 9)>(tk, bits, mode, pack, fp32, hooks, rerun, T, dbg, hbuf, sh,
+                                  sh_waves);
 }
 
 // ---------------------------------------------------------------------------
@@ -435,18 +434,19 @@ __device__ __forceinline__ void reset_product_state(const task &tk) {
   for (uint32_t t = threadIdx.x; t < tk.ntiles; t += blockDim.x) tk.tiles[t * TILE_WORD_STRIDE] = 0u;
 }
 
-// Columns: thread (c, j) with c = tid % C fastest, so that the C columns of a
-// workgroup are adjacent in memory.  grid = (N2 / C, 1 (packed) or 2, tasks).
-__global__ __launch_bounds__(512) void k_col_fwd(const task *tasks, int log_n1, int log_n2,
-                                                 int C, int bits, int pack, twtab T) {
+// Columns: thread (c, j) with c = tid % C fastest, so that the C = 2^lc columns
+// of a workgroup are adjacent in memory.  grid = (N2 / C, 1 (packed) or 2, tasks).
+template <int LOG_N1>
+__global__ __launch_bounds__(512) void k_col_fwd(const task *tasks, int log_n2, int lc, int bits,
+                                                 int pack, twtab T) {
   extern __shared__ double2 hbuf[];
   const uint32_t z = enter_round_up();
   const task tk = after_mode(tasks, z)[blockIdx.z];
   T.tab = after_mode(T.tab, z);
-  const int log_n = log_n1 + log_n2;
-  const int M8 = 1 << (log_n1 - 3);
-  const int c = threadIdx.x % C, j = threadIdx.x / C;
-  const uint32_t n2 = blockIdx.x * C + c;
+  const int log_n = LOG_N1 + log_n2;
+  constexpr int M8 = 1 << (LOG_N1 - 3);
+  const int c = threadIdx.x & ((1 << lc) - 1), j = threadIdx.x >> lc;
+  const uint32_t n2 = (blockIdx.x << lc) + c;
   const bool opb = blockIdx.y != 0;
   if (blockIdx.x == 0 && !opb) reset_product_state(tk);
   uint32_t idx[8], ra[8], rb[8];
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(512) void k_col_fwd(const task *tasks, int log_n1, 
       v[r] = ci_thin_real(digit_value(ra[r], nd, idx[r], bits));
     }
   }
-  fft8_group<false>(v, j, log_n1, hbuf + c, C, T);
+  fft8_group<LOG_N1, false>(v, j, hbuf + c, lc, T);
   ci *Y = opb ? tk.yb : tk.ya;
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = apply_pass_tw(v[q], T, n2, j + q * M8, log_n);
@@ -480,26 +480,26 @@ __global__ __launch_bounds__(512) void k_col_fwd(const task *tasks, int log_n1, 
 
 // Rows (one transform per operand): R rows k1 per workgroup, N2/8 threads per
 // row.  grid = (N1 / R, tasks).
-template <bool WAVE>
-__device__ __forceinline__ void row_body(const task &tk, int log_n1, int log_n2, int R,
-                                         const twtab &T, double2 *hbuf) {
-  const int log_n = log_n1 + log_n2;
-  const int M8 = 1 << (log_n2 - 3);
+template <int LOG_N2, bool WAVE>
+__device__ __forceinline__ void row_body(const task &tk, int log_n1, int R, const twtab &T,
+                                         double2 *hbuf) {
+  const int log_n = log_n1 + LOG_N2;
+  constexpr int M8 = 1 << (LOG_N2 - 3);
   const int g = threadIdx.x / M8, j = threadIdx.x % M8;
   const uint32_t k1 = blockIdx.x * R + g;
-  double2 *hg = hbuf + static_cast<size_t>(g) * lpad_size(size_t(1) << log_n2);
-  const size_t row = static_cast<size_t>(k1) << log_n2;
+  double2 *hg = hbuf + static_cast<size_t>(g) * lpad_size(size_t(1) << LOG_N2);
+  const size_t row = static_cast<size_t>(k1) << LOG_N2;
   ci va[8], vb[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     va[r] = gld(tk.ya, row + j + r * M8);
     vb[r] = gld(tk.yb, row + j + r * M8);
   }
-  fft8_group<WAVE>(va, j, log_n2, hg, 1, T);
-  fft8_group<WAVE>(vb, j, log_n2, hg, 1, T);
+  fft8_group<LOG_N2, WAVE>(va, j, hg, 0, T);
+  fft8_group<LOG_N2, WAVE>(vb, j, hg, 0, T);
 #pragma unroll
   for (int r = 0; r < 8; ++r) va[r] = ci_conj(ci_mul_fast(va[r], vb[r]));
-  fft8_group<WAVE>(va, j, log_n2, hg, 1, T);
+  fft8_group<LOG_N2, WAVE>(va, j, hg, 0, T);
 #pragma unroll
   for (int q = 0; q < 8; ++q) va[q] = ci_conj(apply_pass_tw(va[q], T, j + q * M8, k1, log_n));
   stores_after_loads();
@@ -507,16 +507,13 @@ __device__ __forceinline__ void row_body(const task &tk, int log_n1, int log_n2,
   for (int q = 0; q < 8; ++q) gst(tk.ya, row + j + q * M8, va[q]);
 }
 
-__global__ __launch_bounds__(512) void k_row(const task *tasks, int log_n1, int log_n2, int R,
-                                             twtab T) {
+template <int LOG_N2>
+__global__ __launch_bounds__(512) void k_row(const task *tasks, int log_n1, int R, twtab T) {
   extern __shared__ double2 hbuf[];
   const uint32_t z = enter_round_up();
   const task tk = after_mode(tasks, z)[gridDim.y - 1 - blockIdx.y];  // last written first
   T.tab = after_mode(T.tab, z);
-  if (log_n2 <= 9)
-    row_body<true>(tk, log_n1, log_n2, R, T, hbuf);
-  else
-    row_body<false>(tk, log_n1, log_n2, R, T, hbuf);
+  row_body<LOG_N2, (LOG_N2 <= 9)>(tk, log_n1, R, T, hbuf);
 }
 
 // Row pairs for the packed transform.  Index k = k1 + N1 k2 has
@@ -527,26 +524,27 @@ __global__ __launch_bounds__(512) void k_row(const task *tasks, int log_n1, int 
 // N2/8 threads.  Per row: forward length-N2 DFT, separated pointwise product
 // with the partner row, length-N2 DFT of the conjugate, conjugate inter-pass
 // twiddle.  grid = (N1 / 2 / G, tasks).
-template <bool WAVE>
-__device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int log_n2, int G,
-                                              const twtab &T, double2 *hbuf) {
-  const int log_n = log_n1 + log_n2;
-  const uint32_t N1 = 1u << log_n1, N2 = 1u << log_n2;
-  const int M8 = 1 << (log_n2 - 3);
+template <int LOG_N2, bool WAVE>
+__device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G, const twtab &T,
+                                              double2 *hbuf) {
+  const int log_n = log_n1 + LOG_N2;
+  constexpr uint32_t N2 = 1u << LOG_N2;
+  const uint32_t N1 = 1u << log_n1;
+  constexpr int M8 = 1 << (LOG_N2 - 3);
   const int rg = threadIdx.x / M8;  // row group in the workgroup
   const int j = threadIdx.x % M8;
   const int g = rg >> 1, role = rg & 1;
   const uint32_t p = blockIdx.x * G + g;
   const bool self = p == 0;
   const uint32_t k1 = role == 0 ? p : (self ? N1 / 2 : N1 - p);
-  const size_t rowslots = lpad_size(size_t(1) << log_n2);
+  constexpr size_t rowslots = lpad_size(size_t(1) << LOG_N2);
   double2 *hown = hbuf + static_cast<size_t>(rg) * rowslots;
   double2 *hpart = self ? hown : hbuf + static_cast<size_t>(rg ^ 1) * rowslots;
-  const size_t row = static_cast<size_t>(k1) << log_n2;
+  const size_t row = static_cast<size_t>(k1) << LOG_N2;
   ci v[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) v[r] = gld(tk.ya, row + j + r * M8);
-  fft8_group<WAVE, true>(v, j, log_n2, hown, 1, T);
+  fft8_group<LOG_N2, WAVE, true>(v, j, hown, 0, T);
   // partner values, real halves then imaginary halves (workgroup barriers:
   // the partner row may be another wavefront)
   uint32_t src[8];
@@ -573,7 +571,7 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int lo
     v[r] = ci_conj(separated_product(v[r], W));
   }
   __syncthreads();  // the partner has read this row's buffer
-  fft8_group<WAVE, true>(v, j, log_n2, hown, 1, T);
+  fft8_group<LOG_N2, WAVE, true>(v, j, hown, 0, T);
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = ci_conj(apply_pass_tw(v[q], T, j + q * M8, k1, log_n));
   stores_after_loads();
@@ -581,30 +579,30 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int lo
   for (int q = 0; q < 8; ++q) gst(tk.ya, row + j + q * M8, v[q]);
 }
 
-__global__ __launch_bounds__(512) void k_row_pair(const task *tasks, int log_n1, int log_n2,
-                                                  int G, twtab T) {
+template <int LOG_N2>
+// Three waves per SIMD: the register budget is capped at 168 (a few values spill
+// to scratch for the longest rows), which measured faster than two waves.
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k_row_pair(const task *tasks, int log_n1, int G, twtab T) {
   extern __shared__ double2 hbuf[];
   const uint32_t z = enter_round_up();
   const task tk = after_mode(tasks, z)[gridDim.y - 1 - blockIdx.y];  // last written first
   T.tab = after_mode(T.tab, z);
-  if (log_n2 <= 9)
-    row_pair_body<true>(tk, log_n1, log_n2, G, T, hbuf);
-  else
-    row_pair_body<false>(tk, log_n1, log_n2, G, T, hbuf);
+  row_pair_body<LOG_N2, (LOG_N2 <= 9)>(tk, log_n1, G, T, hbuf);
 }
 
 // Inverse columns + scale + certification.  grid = (N2 / C, tasks).
-__global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n1, int log_n2, int C,
-                                                 int mode, twtab T, double *dbg) {
+template <int LOG_N1>
+__global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n2, int lc, int mode,
+                                                 twtab T, double *dbg) {
   extern __shared__ double2 hbuf[];
   __shared__ cert_shared sh;
   const uint32_t z = enter_round_up();
   const task tk = after_mode(tasks, z)[blockIdx.y];
   T.tab = after_mode(T.tab, z);
-  const int log_n = log_n1 + log_n2;
-  const int M8 = 1 << (log_n1 - 3);
-  const int c = threadIdx.x % C, j = threadIdx.x / C;
-  const uint32_t n2 = blockIdx.x * C + c;
+  const int log_n = LOG_N1 + log_n2;
+  constexpr int M8 = 1 << (LOG_N1 - 3);
+  const int c = threadIdx.x & ((1 << lc) - 1), j = threadIdx.x >> lc;
+  const uint32_t n2 = (blockIdx.x << lc) + c;
   if (threadIdx.x == 0) sh = cert_shared{0ull, 0ull, 0u, 0u};
   ci v[8];
 #pragma unroll
@@ -612,7 +610,7 @@ __global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n1, 
     const uint32_t k1 = j + r * M8;
     v[r] = ci_conj(gld(tk.ya, (static_cast<size_t>(k1) << log_n2) + n2));
   }
-  fft8_group<false>(v, j, log_n1, hbuf + c, C, T);
+  fft8_group<LOG_N1, false>(v, j, hbuf + c, lc, T);
   const double scale = ldexp(1.0, -log_n);
   cert_acc acc{0.0, 0u, 0u, 0u};
 #pragma unroll
@@ -709,16 +707,27 @@ __global__ __launch_bounds__(CARRY_THREADS) void k_carry(const task *tasks, int 
   const uint32_t nout = tk.na + tk.nb;
   const unsigned long long *c = tk.c;
   const long long L = tk.L;
-  if (bits == 8) {
-    for (int t = threadIdx.x; t < CARRY_TILE + 8; t += CARRY_THREADS) {
-      const long long q = base + t;
-      sC[t] = (q >= 0 && q < L) ? gload(c + q) : 0ull;
+  // Every load of a thread is issued before the first is waited for: PER
+  // independent loads in flight per lane instead of one round trip each.
+  constexpr int PER = (CARRY_TILE + 8 + CARRY_THREADS - 1) / CARRY_THREADS;
+  unsigned long long lo[PER], hi[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int t = threadIdx.x + k * CARRY_THREADS;
+    const long long q = base + t;
+    const bool in = t < CARRY_TILE + 8 && q >= 0;
+    if (bits == 8) {
+      lo[k] = (in && q < L) ? gload(c + q) : 0ull;
+      hi[k] = 0ull;
+    } else {
+      lo[k] = (in && 2 * q < L) ? gload(c + 2 * q) : 0ull;
+      hi[k] = (in && 2 * q + 1 < L) ? gload(c + 2 * q + 1) : 0ull;
     }
-  } else {
-    for (int t = threadIdx.x; t < CARRY_TILE + 8; t += CARRY_THREADS) {
-      const long long q = base + t, i0 = 2 * q, i1 = 2 * q + 1;
-      sC[t] = q < 0 ? 0ull : (i0 < L ? gload(c + i0) : 0ull) + 16ull * (i1 < L ? gload(c + i1) : 0ull);
-    }
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int t = threadIdx.x + k * CARRY_THREADS;
+    if (t < CARRY_TILE + 8) sC[t] = lo[k] + 16ull * hi[k];
   }
   __syncthreads();
   auto C = [&](long long q) -> unsigned long long { return sC[q - base]; };
@@ -770,12 +779,23 @@ __global__ void k_scatter(const int *slot_status, const int *order, int n, int *
 
 static constexpr int MAX_DYN_LDS = 131072;
 
+// Kernels are instantiated per transform length: k_small for 2^9..2^12, the
+// column and row passes for column / row lengths 2^6..2^11.  These switches
+// map a run-time length to its instantiation (F is a macro taking the length).
+#define SSA_SMALL_LENGTHS(F) F(9) F(10) F(11) F(12)
+#define SSA_PASS_LENGTHS(F) F(6) F(7) F(8) F(9) F(10) F(11)
+
 hipError_t set_kernel_attributes() {
-  const void *ks[] = {reinterpret_cast<const void *>(&k_small),
-                      reinterpret_cast<const void *>(&k_col_fwd),
-                      reinterpret_cast<const void *>(&k_row),
-                      reinterpret_cast<const void *>(&k_row_pair),
-                      reinterpret_cast<const void *>(&k_col_inv)};
+  const void *ks[] = {
+#define SSA_K_SMALL(L) reinterpret_cast<const void *>(&k_small<L>),
+      SSA_SMALL_LENGTHS(SSA_K_SMALL)
+#undef SSA_K_SMALL
+#define SSA_K_PASS(L)                                                                    \
+  reinterpret_cast<const void *>(&k_col_fwd<L>), reinterpret_cast<const void *>(&k_row<L>), \
+      reinterpret_cast<const void *>(&k_row_pair<L>), reinterpret_cast<const void *>(&k_col_inv<L>),
+      SSA_PASS_LENGTHS(SSA_K_PASS)
+#undef SSA_K_PASS
+  };
   for (const void *k : ks) {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, MAX_DYN_LDS);
     if (e != hipSuccess) return e;
@@ -801,10 +821,25 @@ hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bi
   const int threads = 1 << (log_n - 3);
   const size_t lds = sizeof(double2) * lpad_size(size_t(1) << log_n);
   mark(hk, KIND_SMALL, 0);
-  hipLaunchKernelGGL(k_small, dim3(ntasks), dim3(threads), lds, s, d_tasks, log_n, digit_bits,
-                     cert_mode, pack, fp32, rerun, hooks, to_dev(tw), dbg);
+  switch (log_n) {
+#define SSA_L(L)                                                                               \
+  case L:                                                                                      \
+    hipLaunchKernelGGL(k_small<L>, dim3(ntasks), dim3(threads), lds, s, d_tasks, digit_bits,   \
+                       cert_mode, pack, fp32, rerun, hooks, to_dev(tw), dbg);                  \
+    break;
+    SSA_SMALL_LENGTHS(SSA_L)
+#undef SSA_L
+    default:
+      return hipErrorInvalidValue;
+  }
   mark(hk, KIND_SMALL, 1);
   return hipGetLastError();
+}
+
+static inline int log2_int(int x) {
+  int l = 0;
+  while ((1 << l) < x) ++l;
+  return l;
 }
 
 hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const launch_cfg &cfg,
@@ -812,13 +847,23 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
                             hipStream_t s, const timing_hook *hk) {
   const int l1 = cfg.log_n1, l2 = cfg.log_n2;
   const uint32_t N1 = 1u << l1, N2 = 1u << l2;
+  const int lc = log2_int(cfg.cols);
   const twtab T = to_dev(tw);
+  if (l1 < 6 || l1 > 11 || l2 < 6 || l2 > 11 || (1 << lc) != cfg.cols) return hipErrorInvalidValue;
   {
     const int threads = cfg.cols * static_cast<int>(N1 / 8);
     const size_t lds = sizeof(double2) * lpad_size(N1) * cfg.cols;
+    const dim3 grid(N2 / cfg.cols, cfg.pack ? 1 : 2, ntasks);
     mark(hk, KIND_COL_FWD, 0);
-    hipLaunchKernelGGL(k_col_fwd, dim3(N2 / cfg.cols, cfg.pack ? 1 : 2, ntasks), dim3(threads), lds,
-                       s, d_tasks, l1, l2, cfg.cols, digit_bits, cfg.pack, T);
+    switch (l1) {
+#define SSA_L(L)                                                                                 \
+  case L:                                                                                        \
+    hipLaunchKernelGGL(k_col_fwd<L>, grid, dim3(threads), lds, s, d_tasks, l2, lc, digit_bits,  \
+                       cfg.pack, T);                                                             \
+    break;
+      SSA_PASS_LENGTHS(SSA_L)
+#undef SSA_L
+    }
     mark(hk, KIND_COL_FWD, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -826,18 +871,32 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
   if (cfg.pack) {
     const int threads = 2 * cfg.rows * static_cast<int>(N2 / 8);
     const size_t lds = sizeof(double2) * 2 * lpad_size(N2) * cfg.rows;
+    const dim3 grid(N1 / 2 / cfg.rows, ntasks);
     mark(hk, KIND_ROW, 0);
-    hipLaunchKernelGGL(k_row_pair, dim3(N1 / 2 / cfg.rows, ntasks), dim3(threads), lds, s, d_tasks,
-                       l1, l2, cfg.rows, T);
+    switch (l2) {
+#define SSA_L(L)                                                                                    \
+  case L:                                                                                           \
+    hipLaunchKernelGGL(k_row_pair<L>, grid, dim3(threads), lds, s, d_tasks, l1, cfg.rows, T);      \
+    break;
+      SSA_PASS_LENGTHS(SSA_L)
+#undef SSA_L
+    }
     mark(hk, KIND_ROW, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   } else {
     const int threads = cfg.rows * static_cast<int>(N2 / 8);
     const size_t lds = sizeof(double2) * lpad_size(N2) * cfg.rows;
+    const dim3 grid(N1 / cfg.rows, ntasks);
     mark(hk, KIND_ROW, 0);
-    hipLaunchKernelGGL(k_row, dim3(N1 / cfg.rows, ntasks), dim3(threads), lds, s, d_tasks, l1, l2,
-                       cfg.rows, T);
+    switch (l2) {
+#define SSA_L(L)                                                                               \
+  case L:                                                                                      \
+    hipLaunchKernelGGL(k_row<L>, grid, dim3(threads), lds, s, d_tasks, l1, cfg.rows, T);      \
+    break;
+      SSA_PASS_LENGTHS(SSA_L)
+#undef SSA_L
+    }
     mark(hk, KIND_ROW, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -845,9 +904,17 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
   {
     const int threads = cfg.cols * static_cast<int>(N1 / 8);
     const size_t lds = sizeof(double2) * lpad_size(N1) * cfg.cols;
+    const dim3 grid(N2 / cfg.cols, ntasks);
     mark(hk, KIND_COL_INV, 0);
-    hipLaunchKernelGGL(k_col_inv, dim3(N2 / cfg.cols, ntasks), dim3(threads), lds, s, d_tasks, l1,
-                       l2, cfg.cols, cert_mode, T, dbg);
+    switch (l1) {
+#define SSA_L(L)                                                                                \
+  case L:                                                                                       \
+    hipLaunchKernelGGL(k_col_inv<L>, grid, dim3(threads), lds, s, d_tasks, l2, lc, cert_mode,  \
+                       T, dbg);                                                                 \
+    break;
+      SSA_PASS_LENGTHS(SSA_L)
+#undef SSA_L
+    }
     mark(hk, KIND_COL_INV, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -111,15 +111,15 @@ __device__ __forceinline__ void mr_exchange8(mr v[8], int j, int M8, float4 *h, 
   }
 }
 
-// Forward DFT of M = 2^logM disc intervals, same Stockham schedule as
+// Forward DFT of M = 2^LOGM disc intervals, same Stockham schedule as
 // fft8_group; h holds lpad_size(M) slots of 16 bytes.
-template <bool WAVE>
-__device__ __forceinline__ void mr_fft8_group(mr v[8], int j, int logM, float4 *h, const twtab &T) {
-  const int M8 = 1 << (logM - 3);
+template <int LOGM, bool WAVE>
+__device__ __forceinline__ void mr_fft8_group(mr v[8], int j, float4 *h, const twtab &T) {
+  constexpr int M8 = 1 << (LOGM - 3);
+  constexpr int FIRST = LOGM % 3;
+  constexpr int NR8 = (LOGM - FIRST) / 3;
   const float c8 = static_cast<float>(root(T, 3, 1).x);
-  int logNs = 0;
-  const int first = logM % 3;
-  if (first == 1) {
+  if (FIRST == 1) {
     mr y[8];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -129,8 +129,7 @@ __device__ __forceinline__ void mr_fft8_group(mr v[8], int j, int logM, float4 *
     mr_exchange8<WAVE>(y, j, M8, h, [&](int q) { return 2 * (j + (q >> 1) * M8) + (q & 1); });
 #pragma unroll
     for (int r = 0; r < 8; ++r) v[r] = y[r];
-    logNs = 1;
-  } else if (first == 2) {
+  } else if (FIRST == 2) {
     mr y[8];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
@@ -142,9 +141,10 @@ __device__ __forceinline__ void mr_fft8_group(mr v[8], int j, int logM, float4 *
     mr_exchange8<WAVE>(y, j, M8, h, [&](int q) { return 4 * (j + (q >> 2) * M8) + (q & 3); });
 #pragma unroll
     for (int r = 0; r < 8; ++r) v[r] = y[r];
-    logNs = 2;
   }
-  for (;;) {
+#pragma unroll
+  for (int st = 0; st < NR8; ++st) {
+    const int logNs = FIRST + 3 * st;
     const int Ns = 1 << logNs;
     const int k = j & (Ns - 1);
     if (logNs > 0) {
@@ -152,10 +152,9 @@ __device__ __forceinline__ void mr_fft8_group(mr v[8], int j, int logM, float4 *
       for (int r = 1; r < 8; ++r) v[r] = mr_tw_tab(v[r], root(T, logNs + 3, static_cast<uint32_t>(r * k)));
     }
     mr_radix8(v, c8);
-    if (logNs + 3 == logM) break;
+    if (st + 1 == NR8) break;
     const int base = ((j - k) << 3) + k;
     mr_exchange8<WAVE>(v, j, M8, h, [&](int q) { return base + q * Ns; });
-    logNs += 3;
   }
 }
 
