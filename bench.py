@@ -154,6 +154,60 @@ def measure_batch(binding, torch, digit_bits, steps, precision="fp64", A=None, B
     return res
 
 
+def measure_fft(binding, torch, steps, log_n=18, count=64):
+    """The forward interval DFT alone: `count` transforms of length 2^log_n of
+    thin intervals (packed digits a + i b of seeded random bytes), two passes
+    of the four-step kernels.  Algorithmic bytes: each pass reads and writes
+    every 32-byte element once, 64 N bytes per pass per transform."""
+    N = 1 << log_n
+    rng = np.random.default_rng(2)
+    x = torch.empty((count, N, 4), dtype=torch.float64, device="cuda")
+    for v in range(count):
+        re = torch.from_numpy(rng.integers(0, 256, N).astype(np.float64))
+        im = torch.from_numpy(rng.integers(0, 256, N).astype(np.float64))
+        x[v] = torch.stack([re, re, im, im], dim=1).cuda()
+    y = torch.empty_like(x)
+    plan = binding.Plan(N // 2, N // 2)
+    best = None
+    for shape in ((9, 4, 1), (9, 4, 2), (9, 8, 1), (9, 2, 2), (9, 2, 4), (10, 2, 1), (8, 8, 2)):
+        try:
+            plan.set_config(log_n, *shape)
+        except binding.SsaError:
+            continue
+        for _ in range(2):
+            plan.fft_forward(x, log_n, y=y)
+        t = sum(sum(plan.fft_forward(x, log_n, y=y, timed=True)[2]) for _ in range(3))
+        if best is None or t < best[0]:
+            best = (t, shape)
+    plan.set_config(log_n, *best[1])
+    for _ in range(2):
+        plan.fft_forward(x, log_n, y=y)
+    col = row = 0.0
+    for _ in range(steps):
+        _, l1, ms = plan.fft_forward(x, log_n, y=y, timed=True)
+        col += ms[0]
+        row += ms[1]
+    col /= steps
+    row /= steps
+    yy = y[0].cpu().numpy()
+    assert np.all(np.isfinite(yy)) and np.all(yy[:, 0] <= yy[:, 1]) and np.all(yy[:, 2] <= yy[:, 3])
+    pass_bytes = count * N * 2 * ELEM
+    plan.close()
+    return {
+        "transforms": count,
+        "fft_length": N,
+        "launch_shape": {"log_n1": best[1][0], "cols": best[1][1], "row_pairs": best[1][2]},
+        "ms_per_batch": col + row,
+        "alg_bytes_per_batch": 2 * pass_bytes,
+        "GBps": 2 * pass_bytes / ((col + row) * 1e-3) / 1e9,
+        "frac": 2 * pass_bytes / ((col + row) * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        "col_pass": {"ms": col, "GBps": pass_bytes / (col * 1e-3) / 1e9,
+                     "frac": pass_bytes / (col * 1e-3) / 1e9 / HBM_PEAK_GBPS},
+        "row_pass": {"ms": row, "GBps": pass_bytes / (row * 1e-3) / 1e9,
+                     "frac": pass_bytes / (row * 1e-3) / 1e9 / HBM_PEAK_GBPS},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +217,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 4096-product uneven batch (FP64 base 256 and base 16)")
+    ap.add_argument("--no-fft", action="store_true",
+                    help="skip the standalone forward interval FFT (64 transforms of 2^18)")
     ap.add_argument("--separate-transforms", action="store_true",
                     help="one forward FFT per operand (the fast convolution box literally) "
                          "instead of one FFT of a + i b")
@@ -310,6 +366,9 @@ def main():
     }
     batch.close()
     plan.close()
+
+    if not args.no_fft:
+        result["fft_forward_2p18"] = measure_fft(binding, torch, max(5, args.steps // 5))
 
     if not args.no_batch:
         steps = max(3, args.steps // 10)

@@ -153,6 +153,25 @@ ssa_status ssa_mul_batch(ssa_plan *plan, size_t count, const uint8_t *const *a, 
                          const uint8_t *const *b, const size_t *nb, uint8_t *const *out,
                          int *status_dev);
 
+/* Batched forward interval DFT (section 2.2: X_k = sum_n x_n omega^{n k} with
+ * omega = e^{+2 pi i / N}) over rectangular complex intervals with outward
+ * rounding (section 2.5), by the same two-pass four-step kernels as a product's
+ * forward transform: column DFTs of length N1 times omega_N^{n2 k1}, then row
+ * DFTs of length N2 = N / N1.
+ *  - log_n: 12 < log_n <= the plan's largest transform length; count: 1..65535.
+ *  - x (device, read): count vectors of N = 2^log_n elements in natural order,
+ *    each element 4 doubles {re_lo, re_hi, im_lo, im_hi} with lo <= hi.
+ *  - y (device, written): count vectors of N elements in four-step order: with
+ *    N1 = 2^(*log_n1_host) and N2 = N / N1, element k1 * N2 + k2 of vector v
+ *    encloses X_v[k1 + N1 k2].  x and y must not overlap (SSA_INVALID_ARGUMENT).
+ *  - The launch shape is the plan's for log_n (ssa_plan_get_config; the row pass
+ *    holds 2 * rows rows per workgroup for packed plans, rows otherwise).
+ *  - pass_ms_host (nullable, host, 2 doubles): when given, the plan's stream is
+ *    synchronised and the column and row pass times (ms, HIP events) stored.
+ * Stream-ordered on the plan's stream; allocates nothing when pass_ms_host is NULL. */
+ssa_status ssa_fft_forward(ssa_plan *plan, int log_n, size_t count, const double *x, double *y,
+                           int *log_n1_host, double *pass_ms_host);
+
 /* ---- Launch shapes and the autotuner ----------------------------------------- */
 
 /* Launch shape of the three-pass path (transforms longer than 2^12) for one

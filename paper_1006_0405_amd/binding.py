@@ -35,7 +35,8 @@ EXPORTS = ("ssa_fft_size", "ssa_plan_create", "ssa_plan_destroy", "ssa_mul", "ss
            "ssa_batch_create", "ssa_batch_run", "ssa_batch_stats", "ssa_batch_destroy",
            "ssa_mul_batch", "ssa_debug_enclosures", "ssa_twiddle_table", "ssa_probe_directed",
            "ssa_batch_run_timed", "ssa_batch_kernel_times", "ssa_plan_get_config",
-           "ssa_plan_set_config", "ssa_plan_autotune", "ssa_plan_set_fp32_policy")
+           "ssa_plan_set_config", "ssa_plan_autotune", "ssa_plan_set_fp32_policy",
+           "ssa_fft_forward")
 KERNEL_KINDS = ("small", "col_fwd", "row", "col_inv", "carry", "status")
 
 
@@ -120,6 +121,9 @@ def lib():
                                         ctypes.POINTER(ctypes.c_int)]
         L.ssa_plan_set_fp32_policy.restype = ctypes.c_int
         L.ssa_plan_set_fp32_policy.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
+        L.ssa_fft_forward.restype = ctypes.c_int
+        L.ssa_fft_forward.argtypes = [_vp, ctypes.c_int, _sz, _vp, _vp, ctypes.POINTER(ctypes.c_int),
+                                      _vp]
         L.ssa_probe_directed.restype = ctypes.c_int
         L.ssa_probe_directed.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]
         _lib = L
@@ -265,6 +269,22 @@ class Plan:
             with open(cache, "w") as f:
                 json.dump(table, f, indent=1, sort_keys=True)
         return res
+
+    def fft_forward(self, x, log_n, y=None, timed=False):
+        """Forward interval DFT of x (count x N x 4 float64 device tensor, {re_lo,
+        re_hi, im_lo, im_hi}).  Returns (y in four-step order, log_n1, pass times
+        in ms or None)."""
+        if x.dtype != torch.float64 or not x.is_cuda or x.dim() != 3 or x.shape[1:] != (1 << log_n, 4):
+            raise SsaError("x must be a (count, 2^log_n, 4) float64 device tensor")
+        x = x.contiguous()
+        if y is None:
+            y = torch.empty_like(x)
+        l1 = ctypes.c_int(0)
+        ms = (ctypes.c_double * 2)() if timed else None
+        _check(lib().ssa_fft_forward(self.handle, log_n, x.shape[0], x.data_ptr(), y.data_ptr(),
+                                     ctypes.byref(l1), ctypes.cast(ms, _vp) if timed else None),
+               "ssa_fft_forward")
+        return y, l1.value, (tuple(ms) if timed else None)
 
     def twiddles(self):
         """(table Ntab x 2 float64 device tensor, error bound e, log2 Ntab)."""

@@ -341,6 +341,42 @@ ssa_status ssa_debug_enclosures(ssa_plan *plan, const uint8_t *a, size_t na, con
   return run_single(plan, a, na, b, nb, out, enc_dev, status);
 }
 
+ssa_status ssa_fft_forward(ssa_plan *plan, int log_n, size_t count, const double *x, double *y,
+                           int *log_n1_host, double *pass_ms_host) {
+  if (!plan || !x || !y || !log_n1_host || log_n <= SMALL_MAX_LOG || log_n > plan->log_nmax ||
+      count == 0 || count > 65535)
+    return SSA_INVALID_ARGUMENT;
+  const size_t bytes = (sizeof(ci) * count) << log_n;
+  const char *xb = reinterpret_cast<const char *>(x), *yb = reinterpret_cast<const char *>(y);
+  if (xb < yb + bytes && yb < xb + bytes) return SSA_INVALID_ARGUMENT;  // overlap
+  launch_cfg c = plan->cfg[log_n];
+  if (c.pack) c.rows *= 2;  // the row-pair kernel's workgroup holds 2 rows per pair
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  if (pass_ms_host) {
+    for (hipEvent_t &e : ev)
+      if (!hip_ok(hipEventCreate(&e))) {
+        for (hipEvent_t f : ev)
+          if (f) hipEventDestroy(f);
+        return SSA_DEVICE_ERROR;
+      }
+  }
+  hipStream_t s = plan->stream;
+  bool ok = hip_ok(launch_fft_forward(x, y, static_cast<int>(count), c, tw_of(plan), s,
+                                      pass_ms_host ? ev : nullptr));
+  if (ok && pass_ms_host) {
+    float m0 = 0.f, m1 = 0.f;
+    ok = hip_ok(hipEventSynchronize(ev[2])) && hip_ok(hipEventElapsedTime(&m0, ev[0], ev[1])) &&
+         hip_ok(hipEventElapsedTime(&m1, ev[1], ev[2]));
+    pass_ms_host[0] = m0;
+    pass_ms_host[1] = m1;
+  }
+  for (hipEvent_t f : ev)
+    if (f) hipEventDestroy(f);
+  if (!ok) return SSA_DEVICE_ERROR;
+  *log_n1_host = c.log_n1;
+  return SSA_OK;
+}
+
 ssa_status ssa_plan_set_fp32_policy(ssa_plan *plan, int max_coeffs, int force_fail) {
   if (!plan || plan->opts.precision != SSA_FP32_FALLBACK || max_coeffs < 0 ||
       max_coeffs > (1 << SMALL_MAX_LOG) || (force_fail != 0 && force_fail != 1))

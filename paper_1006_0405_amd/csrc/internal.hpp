@@ -95,6 +95,11 @@ hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bi
 hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const launch_cfg &cfg,
                             int digit_bits, int cert_mode, const twtab_host &tw, double *dbg,
                             hipStream_t s, const timing_hook *hk = nullptr);
+// Batched forward DFT of `count` vectors of N = N1 N2 public-layout intervals
+// (x -> y, four-step output order); ev (nullable): 3 events recorded before the
+// column pass, between the passes and after the row pass.
+hipError_t launch_fft_forward(const double *x, double *y, int count, const launch_cfg &cfg,
+                              const twtab_host &tw, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_carry(const task *d_tasks, int ntasks, uint32_t max_tiles, int digit_bits,
                         hipStream_t s, const timing_hook *hk = nullptr);
 hipError_t launch_status(const task *d_tasks, int ntasks, int *d_status, hipStream_t s,

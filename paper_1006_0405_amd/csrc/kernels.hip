@@ -632,6 +632,72 @@ __global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n2, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched forward interval DFT (section 2.2) of caller-supplied intervals, the
+// same two passes as the product's forward transform without the digits.
+// Public element layout: 4 doubles {re_lo, re_hi, im_lo, im_hi}; lower bounds
+// are negated on load and back on store (exact).
+
+__device__ __forceinline__ ci load_public(const double *x, size_t idx) {
+  const ci v = gld(reinterpret_cast<const ci *>(x), idx);  // {re_lo, re_hi, im_lo, im_hi}
+  return ci{-v.rn, v.rh, -v.in, v.ih};
+}
+__device__ __forceinline__ void store_public(double *y, size_t idx, const ci &v) {
+  gst(reinterpret_cast<ci *>(y), idx, ci{-v.rn, v.rh, -v.in, v.ih});
+}
+
+// Columns: length-N1 DFTs over n1 of x[n1 N2 + n2], times omega_N^{n2 k1}, to
+// y[k1 N2 + n2].  Thread (c, j), C = 2^lc adjacent columns per workgroup.
+// grid = (N2 / C, vectors).
+template <int LOG_N1>
+__global__ __launch_bounds__(512) void k_fft_col(const double *x, double *y, int log_n2, int lc,
+                                                 twtab T) {
+  extern __shared__ double2 hbuf[];
+  const uint32_t z = enter_round_up();
+  x = after_mode(x, z);
+  T.tab = after_mode(T.tab, z);
+  const int log_n = LOG_N1 + log_n2;
+  constexpr int M8 = 1 << (LOG_N1 - 3);
+  const int c = threadIdx.x & ((1 << lc) - 1), j = threadIdx.x >> lc;
+  const uint32_t n2 = (blockIdx.x << lc) + c;
+  const size_t base = static_cast<size_t>(blockIdx.y) << log_n;
+  ci v[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = load_public(x, base + (static_cast<size_t>(j + r * M8) << log_n2) + n2);
+  fft8_group<LOG_N1, false>(v, j, hbuf + c, lc, T);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = apply_pass_tw(v[q], T, n2, j + q * M8, log_n);
+  stores_after_loads();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const ci w = v[q];
+    gst(reinterpret_cast<ci *>(y), base + (static_cast<size_t>(j + q * M8) << log_n2) + n2, w);
+  }
+}
+
+// Rows, in place: length-N2 DFT of row k1, element k2 of the row then encloses
+// X[k1 + N1 k2].  R rows per workgroup, N2/8 threads per row.  grid = (N1 / R,
+// vectors).
+template <int LOG_N2>
+__global__ __launch_bounds__(512) void k_fft_row(double *y, int log_n1, int R, twtab T) {
+  extern __shared__ double2 hbuf[];
+  const uint32_t z = enter_round_up();
+  y = after_mode(y, z);
+  T.tab = after_mode(T.tab, z);
+  constexpr int M8 = 1 << (LOG_N2 - 3);
+  const int g = threadIdx.x / M8, j = threadIdx.x % M8;
+  const uint32_t k1 = blockIdx.x * R + g;
+  double2 *hg = hbuf + static_cast<size_t>(g) * lpad_size(size_t(1) << LOG_N2);
+  const size_t row = (static_cast<size_t>(blockIdx.y) << (log_n1 + LOG_N2)) +
+                     (static_cast<size_t>(k1) << LOG_N2);
+  ci v[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = gld(reinterpret_cast<const ci *>(y), row + j + r * M8);
+  fft8_group<LOG_N2, (LOG_N2 <= 9)>(v, j, hg, 0, T);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) store_public(y, row + j + q * M8, v[q]);
+}
+
 // Decoupled look-back (Merrill & Garland): tile status word = flag << 2 | bits,
 // flag 1: aggregate (G << 1 | P), flag 2: inclusive carry-out.  The word holds
 // all the information a reader needs, so relaxed device-scope atomics suffice;
@@ -792,7 +858,8 @@ hipError_t set_kernel_attributes() {
 #undef SSA_K_SMALL
 #define SSA_K_PASS(L)                                                                    \
   reinterpret_cast<const void *>(&k_col_fwd<L>), reinterpret_cast<const void *>(&k_row<L>), \
-      reinterpret_cast<const void *>(&k_row_pair<L>), reinterpret_cast<const void *>(&k_col_inv<L>),
+      reinterpret_cast<const void *>(&k_row_pair<L>), reinterpret_cast<const void *>(&k_col_inv<L>), \
+      reinterpret_cast<const void *>(&k_fft_col<L>), reinterpret_cast<const void *>(&k_fft_row<L>),
       SSA_PASS_LENGTHS(SSA_K_PASS)
 #undef SSA_K_PASS
   };
@@ -920,6 +987,50 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
     if (e != hipSuccess) return e;
   }
   (void)log_n;
+  return hipSuccess;
+}
+
+hipError_t launch_fft_forward(const double *x, double *y, int count, const launch_cfg &cfg,
+                              const twtab_host &tw, hipStream_t s, hipEvent_t *ev) {
+  const int l1 = cfg.log_n1, l2 = cfg.log_n2;
+  const uint32_t N1 = 1u << l1, N2 = 1u << l2;
+  const int lc = log2_int(cfg.cols);
+  const twtab T = to_dev(tw);
+  if (l1 < 6 || l1 > 11 || l2 < 6 || l2 > 11 || (1 << lc) != cfg.cols || count < 1 || count > 65535)
+    return hipErrorInvalidValue;
+  if (ev) hipEventRecord(ev[0], s);
+  {
+    const int threads = cfg.cols * static_cast<int>(N1 / 8);
+    const size_t lds = sizeof(double2) * lpad_size(N1) * cfg.cols;
+    const dim3 grid(N2 / cfg.cols, count);
+    switch (l1) {
+#define SSA_L(L)                                                                                \
+  case L:                                                                                       \
+    hipLaunchKernelGGL(k_fft_col<L>, grid, dim3(threads), lds, s, x, y, l2, lc, T);            \
+    break;
+      SSA_PASS_LENGTHS(SSA_L)
+#undef SSA_L
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (ev) hipEventRecord(ev[1], s);
+  {
+    const int threads = cfg.rows * static_cast<int>(N2 / 8);
+    const size_t lds = sizeof(double2) * lpad_size(N2) * cfg.rows;
+    const dim3 grid(N1 / cfg.rows, count);
+    switch (l2) {
+#define SSA_L(L)                                                                                \
+  case L:                                                                                       \
+    hipLaunchKernelGGL(k_fft_row<L>, grid, dim3(threads), lds, s, y, l1, cfg.rows, T);         \
+    break;
+      SSA_PASS_LENGTHS(SSA_L)
+#undef SSA_L
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (ev) hipEventRecord(ev[2], s);
   return hipSuccess;
 }
 

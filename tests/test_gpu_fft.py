@@ -1,0 +1,156 @@
+"""GPU parity tests of the batched forward interval DFT (ssa_fft_forward).
+
+The DFT is the paper's (section 2.2, omega = e^{+2 pi i/N}) over rectangular
+complex intervals with outward rounding (section 2.5).  Enclosures are not
+unique, so parity with the oracle's DFT (oracle.dft, radix-2 recursion in
+fesetround interval arithmetic) is checked by intersection: both enclose the
+same exact DFT, so every GPU interval must meet the oracle's.  Exact values
+(DFT special cases of the section 2.2 lemma, and 200-bit mpmath sums at sampled
+indices) must lie inside the GPU enclosures.  The maximum half-widths are
+reported side by side.
+"""
+import mpmath
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1006_0405_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+
+def natural(y, log_n, log_n1):
+    """Four-step order (element k1 * N2 + k2 encloses X[k1 + N1 k2]) to natural order."""
+    N1, N2 = 1 << log_n1, 1 << (log_n - log_n1)
+    return y.reshape(-1, N1, N2, 4).transpose(0, 2, 1, 3).reshape(-1, N1 * N2, 4)
+
+
+def thin(re, im):
+    x = np.zeros(re.shape + (4,))
+    x[..., 0] = x[..., 1] = re
+    x[..., 2] = x[..., 3] = im
+    return x
+
+
+def gpu_fft(plan, x, log_n, shape=None):
+    if shape is not None:
+        plan.set_config(log_n, *shape)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    y, l1, _ = plan.fft_forward(xt, log_n)
+    return natural(y.cpu().numpy(), log_n, l1)
+
+
+def assert_intersects(g, o):
+    for lo, hi in ((0, 1), (2, 3)):
+        assert np.all(g[..., lo] <= g[..., hi])
+        bad = np.maximum(g[..., lo], o[..., lo]) > np.minimum(g[..., hi], o[..., hi])
+        assert not bad.any(), "disjoint enclosures at %s" % np.argwhere(bad)[:5].tolist()
+
+
+def half_width(e):
+    return max(float(np.max(e[..., 1] - e[..., 0])), float(np.max(e[..., 3] - e[..., 2]))) / 2
+
+
+@pytest.mark.parametrize("log_n,shape", [(13, None), (14, (7, 8, 2)), (15, (8, 2, 2)),
+                                         (16, (10, 2, 4))])
+def test_fft_meets_oracle(log_n, shape):
+    N = 1 << log_n
+    rng = np.random.default_rng(100 + log_n)
+    x = np.zeros((3, N, 4))
+    # thin integer inputs (the packed digits a + i b of a product) ...
+    x[0] = thin(rng.integers(0, 256, N).astype(float), rng.integers(0, 256, N).astype(float))
+    # ... a ragged tail of zeros (zero padding) ...
+    x[1] = thin(np.where(np.arange(N) < N - 1234, 255.0, 0.0), np.zeros(N))
+    # ... and genuinely wide intervals with real-valued end points
+    c = rng.standard_normal((N, 2)) * 1e3
+    w = rng.random((N, 2)) * 1e-3
+    x[2, :, 0], x[2, :, 1] = c[:, 0] - w[:, 0], c[:, 0] + w[:, 0]
+    x[2, :, 2], x[2, :, 3] = c[:, 1] - w[:, 1], c[:, 1] + w[:, 1]
+    plan = binding.Plan(N, N)
+    g = gpu_fft(plan, x, log_n, shape)
+    for v in range(3):
+        o = oracle.dft(log_n, x[v])
+        assert_intersects(g[v], o)
+        print("N=2^%d vector %d: half-width GPU %.3g, oracle %.3g" % (log_n, v, half_width(g[v]),
+                                                                     half_width(o)))
+    plan.close()
+
+
+def test_fft_lemma_special_cases():
+    log_n = 13
+    N = 1 << log_n
+    x = np.zeros((3, N, 4))
+    x[0] = thin((np.arange(N) == 0).astype(float), np.zeros(N))   # e_0 -> all ones
+    x[1] = thin(np.ones(N), np.zeros(N))                           # ones -> N e_0
+    x[2] = thin((np.arange(N) == 1).astype(float), np.zeros(N))   # e_1 -> omega^k
+    plan = binding.Plan(N, N)
+    g = gpu_fft(plan, x, log_n)
+    one = np.zeros((N, 2))
+    one[:, 0] = 1.0
+    scaled = np.zeros((N, 2))
+    scaled[0, 0] = N
+    for v, want in ((0, one), (1, scaled)):
+        assert np.all(g[v, :, 0] <= want[:, 0]) and np.all(want[:, 0] <= g[v, :, 1])
+        assert np.all(g[v, :, 2] <= want[:, 1]) and np.all(want[:, 1] <= g[v, :, 3])
+    mpmath.mp.prec = 200
+    for k in list(range(0, N, 37)) + [N // 8, N // 4, N // 2, 3 * N // 4, N - 1]:
+        ang = 2 * mpmath.pi * k / N
+        cr, si = mpmath.cos(ang), mpmath.sin(ang)
+        assert mpmath.mpf(g[2, k, 0]) <= cr <= mpmath.mpf(g[2, k, 1]), k
+        assert mpmath.mpf(g[2, k, 2]) <= si <= mpmath.mpf(g[2, k, 3]), k
+    plan.close()
+
+
+def test_fft_contains_exact_dft_samples():
+    """X_k = sum_n x_n e^{2 pi i n k/N} in 200-bit arithmetic at sampled k."""
+    log_n = 13
+    N = 1 << log_n
+    rng = np.random.default_rng(7)
+    re = rng.integers(0, 256, N)
+    im = rng.integers(0, 256, N)
+    plan = binding.Plan(N, N)
+    g = gpu_fft(plan, thin(re.astype(float), im.astype(float))[None], log_n)[0]
+    mpmath.mp.prec = 200
+    nz = [(int(n), mpmath.mpc(int(re[n]), int(im[n]))) for n in range(N) if re[n] or im[n]]
+    roots = {}
+    for k in (0, 1, 2, 5, 1000, N // 2 + 3, N - 1):
+        s = mpmath.mpc(0)
+        for n, xn in nz:
+            e = (n * k) % N  # omega^{n k} = omega^e, omega = e^{2 pi i/N}
+            if e not in roots:
+                roots[e] = mpmath.expjpi(mpmath.mpf(2 * e) / N)
+            s += xn * roots[e]
+        assert mpmath.mpf(g[k, 0]) <= s.real <= mpmath.mpf(g[k, 1]), k
+        assert mpmath.mpf(g[k, 2]) <= s.imag <= mpmath.mpf(g[k, 3]), k
+    plan.close()
+
+
+def test_fft_2p18_bench_shape_meets_oracle():
+    """Full length 2^18 in the launch shape the benchmark times (column length
+    2^9, 4 columns per workgroup), one vector against the oracle everywhere."""
+    log_n = 18
+    N = 1 << log_n
+    rng = np.random.default_rng(2)
+    x = thin(rng.integers(0, 256, N).astype(float), rng.integers(0, 256, N).astype(float))[None]
+    plan = binding.Plan(N // 2, N // 2)
+    o = oracle.dft(log_n, x[0])
+    for shape in ((9, 4, 1), (9, 4, 2)):
+        g = gpu_fft(plan, x, log_n, shape)[0]
+        assert_intersects(g, o)
+        print("2^18 shape %s: half-width GPU %.3g, oracle %.3g" % (shape, half_width(g),
+                                                                   half_width(o)))
+    plan.close()
+
+
+def test_fft_rejects_bad_arguments():
+    plan = binding.Plan(4096, 4096)
+    x = torch.zeros((1, 1 << 13, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(binding.SsaError):
+        plan.fft_forward(x, 13, y=x)                      # in place: overlap
+    with pytest.raises(binding.SsaError):
+        plan.fft_forward(torch.zeros((1, 1 << 12, 4), dtype=torch.float64, device="cuda"), 12)
+    big = torch.zeros((1, 1 << 14, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(binding.SsaError):
+        plan.fft_forward(big, 14)                         # above the plan's largest length
+    plan.close()
