@@ -360,7 +360,6 @@ __device__ __forceinline__ void small_body(const task &tk, int bits, int mode, i
     st->too_wide = sh.too_wide;
     st->internal = sh.internal;
     st->carry_err = 0u;
-    st->ticket = 0u;
     st->fallback = (rerun && tk.fp32 != 0u) ? 1u : 0u;
     st->fp32 = tk.fp32;
   }
@@ -427,7 +426,6 @@ __device__ __forceinline__ void reset_product_state(const task &tk) {
     tk.st->too_wide = 0u;
     tk.st->internal = 0u;
     tk.st->carry_err = 0u;
-    tk.st->ticket = 0u;
     tk.st->fallback = 0u;
     tk.st->fp32 = 0u;
   }
@@ -702,11 +700,12 @@ __global__ __launch_bounds__(512) void k_fft_row(double *y, int log_n1, int R, t
 // flag 1: aggregate (G << 1 | P), flag 2: inclusive carry-out.  The word holds
 // all the information a reader needs, so relaxed device-scope atomics suffice;
 // acquire/release at device scope would also write back or invalidate the
-// XCD's L2 on every poll.  Tile numbers
-// come from a ticket counter in start order, so every tile looked at belongs to
-// a workgroup that is already running and never waits itself before
-// publishing its aggregate: the wait always ends.  A generous spin limit turns
-// an impossible hang into a reported error instead.
+// XCD's L2 on every poll.  A tile is its workgroup's blockIdx.x and tiles of a
+// product are consecutive in the grid's x dimension, so every tile looked at
+// belongs to a workgroup dispatched earlier, which publishes its aggregate
+// before it waits itself: with in-order workgroup dispatch the wait always
+// ends.  A generous spin limit turns a hang into a reported error
+// (carry_err, SSA_DEVICE_ERROR) should that order ever not hold.
 static constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
 __device__ uint32_t lookback(uint32_t *tiles, uint32_t tile, uint32_t G, uint32_t P,
@@ -751,23 +750,16 @@ __device__ uint32_t lookback(uint32_t *tiles, uint32_t tile, uint32_t G, uint32_
   return cin;
 }
 
-// grid = (max tiles, tasks), CARRY_THREADS threads.  The tile's coefficients
+// grid = (max tiles, tasks), CARRY_THREADS threads, tile = blockIdx.x.  The tile's coefficients
 // (with 8 before it) are staged in LDS by coalesced loads first, so the six
 // overlapping reads per position hit LDS and each lane issues few global loads.
 __global__ __launch_bounds__(CARRY_THREADS) void k_carry(const task *tasks, int bits) {
   __shared__ uint32_t sh_waves[CARRY_THREADS / 64];
-  __shared__ uint32_t sh_tile;
-  __shared__ uint32_t sh_failed;
   __shared__ unsigned long long sC[CARRY_TILE + 8];
   const task tk = tasks[gridDim.y - 1 - blockIdx.y];  // last written first
-  if (blockIdx.x >= tk.ntiles) return;
-  if (threadIdx.x == 0) {
-    sh_tile = atomicAdd(&tk.st->ticket, 1u);
-    sh_failed = (tk.st->too_wide + tk.st->internal) != 0u ? 1u : 0u;
-  }
-  __syncthreads();
-  const uint32_t tile = sh_tile;
-  const bool failed = sh_failed != 0u;
+  const uint32_t tile = blockIdx.x;
+  if (tile >= tk.ntiles) return;
+  const bool failed = (tk.st->too_wide + tk.st->internal) != 0u;
   const long long p0 = static_cast<long long>(tile) * CARRY_TILE;
   const long long base = p0 - 8;
   const uint32_t nout = tk.na + tk.nb;
