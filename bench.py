@@ -208,6 +208,51 @@ def measure_fft(binding, torch, steps, log_n=18, count=64):
     }
 
 
+def measure_singles(binding, torch, reps=10):
+    """One product at a time through ssa_mul (its host synchronisation included):
+    the 1,024-digit product (N = 2^11), the 75,000-digit products (N = 2^18,
+    uniform random and all-0xFF) and the 1,000,000-byte products split into
+    base-16 digits (N = 2^22, uniform random and all-0xFF).  Median latency of
+    `reps` calls after two warm-up calls; every product checked against
+    CPython's integer product."""
+    from paper_1006_0405_amd.workloads import all_ff, pair
+    cases = [("1024x1024_base256", 8, lambda: pair(1, 1024)),
+             ("75000x75000_base256_random", 8, lambda: pair(2, 75_000)),
+             ("75000x75000_base256_all_ff", 8, lambda: (all_ff(75_000), all_ff(75_000))),
+             ("1000000x1000000_base16_random", 4, lambda: pair(5, 1_000_000)),
+             ("1000000x1000000_base16_all_ff", 4, lambda: (all_ff(1_000_000), all_ff(1_000_000)))]
+    out = {}
+    plans = {}
+    for name, bits, make in cases:
+        a, b = make()
+        key = (bits, len(a))
+        if key not in plans:
+            plans[key] = binding.Plan(len(a), len(b), digit_bits=bits)
+        plan = plans[key]
+        da = torch.from_numpy(a).cuda()
+        db = torch.from_numpy(b).cuda()
+        res = torch.empty(len(a) + len(b), dtype=torch.uint8, device="cuda")
+        for _ in range(2):
+            st, _ = plan.mul(da, db, out=res)
+        want = (int.from_bytes(a.tobytes(), "little") *
+                int.from_bytes(b.tobytes(), "little")).to_bytes(len(a) + len(b), "little")
+        assert st == binding.SSA_OK and res.cpu().numpy().tobytes() == want, name
+        lat = []
+        n = reps if len(a) < 500_000 else max(3, reps // 2)
+        for _ in range(n):
+            t = time.perf_counter()
+            plan.mul(da, db, out=res)
+            lat.append(time.perf_counter() - t)
+        s = plan.stats()
+        ms = float(np.median(lat) * 1e3)
+        out[name] = {"fft_length": 1 << s["log_n"], "digit_bits": bits, "latency_ms": ms,
+                     "products_per_s": 1e3 / ms, "max_radius": s["max_radius"],
+                     "status": "certified"}
+    for p in plans.values():
+        p.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +262,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 4096-product uneven batch (FP64 base 256 and base 16)")
+    ap.add_argument("--no-singles", action="store_true",
+                    help="skip the one-at-a-time products (1,024, 75,000 and 1,000,000 bytes)")
     ap.add_argument("--no-fft", action="store_true",
                     help="skip the standalone forward interval FFT (64 transforms of 2^18)")
     ap.add_argument("--separate-transforms", action="store_true",
@@ -366,6 +413,9 @@ def main():
     }
     batch.close()
     plan.close()
+
+    if not args.no_singles:
+        result["single_products"] = measure_singles(binding, torch)
 
     if not args.no_fft:
         result["fft_forward_2p18"] = measure_fft(binding, torch, max(5, args.steps // 5))
