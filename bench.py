@@ -103,6 +103,30 @@ def traffic_for(kernel, launches_products):
     return per_product * launches_products
 
 
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (an FMA counts two)
+
+
+def fp64_rate(kinds, ms_per_launch):
+    """FP64 flop rate of each kernel over a launch: executed FP64 add, mul and fma
+    wave instructions per launch from committed rocprofv3 counter summaries (64
+    lanes each, an fma counting two) divided by the launch time measured here;
+    None when the counters were taken on other kernel sources."""
+    p = os.path.join(ROOT, "profiles", "fp64.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    out = {}
+    for k in kinds:
+        if k in d["kernels"] and ms_per_launch.get(k):
+            fl = d["kernels"][k]["flops_per_launch"]
+            tf = fl / (ms_per_launch[k] * 1e-3) / 1e12
+            out[k] = {"flops_per_launch": fl, "tflops": tf, "peak": FP64_PEAK_TFLOPS,
+                      "frac": tf / FP64_PEAK_TFLOPS}
+    return out or None
+
+
 def measure_batch(binding, torch, digit_bits, steps, precision="fp64", A=None, B=None):
     """Default: the 4096-product batch, operand lengths log-uniform in
     [64, 16384] bytes (seed 3).  One graph launch per step; every product
@@ -405,6 +429,7 @@ def main():
         "digits_per_s": value * 2 * NBYTES,
         "alg_GBps_whole_step": step_bytes / (elapsed / args.steps) / 1e9,
         "kernel_ms_per_launch": per_launch_ms,
+        "fp64": fp64_rate(kinds, per_launch_ms),
         "graph_products_per_s": graph_rate,
         "single_product_latency_ms": latency_ms,
         "max_radius": max_rad,
