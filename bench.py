@@ -413,7 +413,7 @@ def main():
             "fft_length": N,
             "digit_bits": 8,
             "transform": "one complex FFT of a + i b" if packed else "one FFT per operand",
-            "launch_shape": {k: tuned[k] for k in ("log_n1", "cols", "rows")},
+            "launch_shape": {k: tuned[k] for k in ("log_n1", "cols", "rows", "persistent")},
         },
         "roofline": {
             "bound": "hbm",

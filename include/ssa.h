@@ -176,13 +176,16 @@ ssa_status ssa_fft_forward(ssa_plan *plan, int log_n, size_t count, const double
 
 /* Launch shape of the three-pass path (transforms longer than 2^12) for one
  * transform length 2^log_n: column transforms of length 2^log_n1 (rows of
- * 2^(log_n - log_n1)), `cols` adjacent columns per column-pass workgroup, and
- * `rows` rows (row pairs for the packed transform) per row-pass workgroup. */
+ * 2^(log_n - log_n1)), `cols` adjacent columns per column-pass workgroup,
+ * `rows` rows (row pairs for the packed transform) per row-pass workgroup, and
+ * whether the row pass runs persistent. */
 typedef struct {
   int log_n1;
   int cols;
   int rows;
-  int reserved;
+  int persistent;  /* 1: the row pass runs as a persistent kernel (as many workgroups as
+                      are resident) that prefetches its next rows while computing the
+                      current ones; packed plans with rows of at most 2^9 points only */
 } ssa_launch_config;
 
 ssa_status ssa_plan_get_config(const ssa_plan *plan, int log_n, ssa_launch_config *cfg_host);

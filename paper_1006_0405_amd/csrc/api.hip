@@ -42,6 +42,7 @@ launch_cfg default_cfg(int log_n, int pack) {
   const int N1 = 1 << c.log_n1, N2 = 1 << c.log_n2;
   c.cols = std::max(2, std::min(32, 2048 / N1));
   c.pack = pack;
+  c.persist = 0;
   const int t = N2 / 8;  // threads per row
   if (pack)
     c.rows = std::max(1, std::min(N1 / 2, 128 / t));
@@ -67,6 +68,11 @@ bool cfg_valid(const launch_cfg &c, int log_n) {
   const int rt = per * c.rows * N2 / 8;
   if (rt > 512 || rt % 64) return false;
   if (static_cast<size_t>(per) * c.rows * (N2 + N2 / 8) * 16 > 81920) return false;
+  if (c.persist != 0 && c.persist != 1) return false;
+  // the persistent row pass: packed rows of one wavefront, twiddle levels in LDS
+  if (c.persist && (!c.pack || c.log_n2 > 9 ||
+                    (2 * static_cast<size_t>(c.rows) * (N2 + N2 / 8) + (size_t(2) << c.log_n2)) * 16 > 81920))
+    return false;
   return true;
 }
 
@@ -690,13 +696,14 @@ static launch_cfg from_public(const ssa_launch_config &c, int log_n, int pack) {
   r.cols = c.cols;
   r.rows = c.rows;
   r.pack = pack;
+  r.persist = c.persistent;
   return r;
 }
 
 ssa_status ssa_plan_get_config(const ssa_plan *plan, int log_n, ssa_launch_config *cfg) {
   if (!plan || !cfg || log_n <= SMALL_MAX_LOG || log_n > MAX_LOG_N) return SSA_INVALID_ARGUMENT;
   const launch_cfg &c = plan->cfg[log_n];
-  *cfg = ssa_launch_config{c.log_n1, c.cols, c.rows, 0};
+  *cfg = ssa_launch_config{c.log_n1, c.cols, c.rows, c.persist};
   return SSA_OK;
 }
 
@@ -769,8 +776,9 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
   bool ok = true;
   for (int l1 = 6; l1 <= 11 && ok; ++l1)
     for (int cols = 1; cols <= 32 && ok; cols *= 2)
-      for (int rows = 1; rows <= 64 && ok; rows *= 2) {
-        launch_cfg c{l1, log_n - l1, cols, rows, pack};
+      for (int rows = 1; rows <= 64 && ok; rows *= 2)
+        for (int persist = 0; persist <= 1 && ok; ++persist) {
+        launch_cfg c{l1, log_n - l1, cols, rows, pack, persist};
         if (!cfg_valid(c, log_n)) continue;
         plan->cfg[log_n] = c;
         ok = hip_ok(enqueue_batch(bt, s, nullptr));  // warm-up
@@ -797,7 +805,7 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
     hipGetLastError();
     return SSA_DEVICE_ERROR;
   }
-  *best = ssa_launch_config{bestc.log_n1, bestc.cols, bestc.rows, 0};
+  *best = ssa_launch_config{bestc.log_n1, bestc.cols, bestc.rows, bestc.persist};
   *best_ms_host = bestms;
   if (tried_host) *tried_host = tried;
   return SSA_OK;

@@ -65,5 +65,18 @@ struct twtab {
 __device__ __forceinline__ double2 root(const twtab &T, int l, uint32_t u) {
   return T.tab[(1u << l) + u];
 }
+// The same levels copied into LDS (entries below 2^(l+1) for the levels a
+// kernel uses), read through a local-address-space pointer so the reads are
+// LDS instructions that never wait on global memory operations.
+typedef __attribute__((address_space(3))) const double *lds_dp;
+struct twtab_lds {
+  lds_dp tab;  // 2 doubles (cos, sin) per entry
+  int log_ntab;
+  double e;
+};
+__device__ __forceinline__ double2 root(const twtab_lds &T, int l, uint32_t u) {
+  const uint32_t i = 2u * ((1u << l) + u);
+  return make_double2(T.tab[i], T.tab[i + 1]);
+}
 
 }  // namespace ssa

@@ -114,8 +114,8 @@ __device__ __forceinline__ void exchange8(ci v[8], int j, int M8, double2 *h, in
 // half-element exchange buffer; element i lives at h[lpad(i) << lis].  With
 // WAVE the group must be exactly the lanes of (part of) one wavefront;
 // otherwise every thread of the workgroup must call this with the same M.
-template <int LOGM, bool WAVE, bool PF = false>
-__device__ __forceinline__ void fft8_group(ci v[8], int j, double2 *h, int lis, const twtab &T) {
+template <int LOGM, bool WAVE, bool PF = false, class TT = twtab>
+__device__ __forceinline__ void fft8_group(ci v[8], int j, double2 *h, int lis, const TT &T) {
   static_assert(LOGM >= 3, "length-8 groups at least");
   constexpr int M8 = 1 << (LOGM - 3);
   constexpr int FIRST = LOGM % 3;           // radix-2 (1) or radix-4 (2) first stage, or none (0)

@@ -60,6 +60,7 @@ struct launch_cfg {
   int cols;    // columns per workgroup in the column passes
   int rows;    // rows (row pairs when packed) per workgroup in the row pass
   int pack;    // 1: one complex transform of a + i b; 0: one transform per operand
+  int persist; // 1: persistent row-pair pass with next-item prefetch (pack, rows <= 2^9)
 };
 
 struct twtab_host {

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "fft8.hpp"
 #include "mr32.hpp"
 #include "internal.hpp"
@@ -588,6 +590,105 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
   row_pair_body<LOG_N2, (LOG_N2 <= 9)>(tk, log_n1, G, T, hbuf);
 }
 
+// Persistent form of k_row_pair for rows of at most 2^9 points: gridDim.x
+// workgroups (as many as are resident at once) walk the (product, pair group)
+// items, products in descending order, and each prefetches the next item's rows
+// into registers while it computes the current one, so that the global-memory
+// latency of one item overlaps the arithmetic of the previous one.  The
+// twiddles of the row DFTs are copied once into LDS (levels up to 2^LOG_N2), so
+// the stage twiddle reads do not wait behind the stores of the previous item
+// (one counter tracks both global loads and stores).
+template <int LOG_N2>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_row_pair_p(
+    const task *tasks, int ntasks, int log_n1, int G, twtab T) {
+  static_assert(LOG_N2 <= 9, "rows of one wavefront");
+  extern __shared__ double2 hbuf[];
+  const uint32_t z = enter_round_up();
+  tasks = after_mode(tasks, z);
+  T.tab = after_mode(T.tab, z);
+  constexpr uint32_t N2 = 1u << LOG_N2;
+  constexpr int M8 = 1 << (LOG_N2 - 3);
+  constexpr size_t rowslots = lpad_size(size_t(1) << LOG_N2);
+  const int log_n = log_n1 + LOG_N2;
+  const uint32_t N1 = 1u << log_n1;
+  const int rg = threadIdx.x / M8, j = threadIdx.x % M8;
+  const int g = rg >> 1, role = rg & 1;
+  const uint32_t per_task = N1 / 2 / G, total = per_task * ntasks;
+  double2 *tl = hbuf + static_cast<size_t>(2 * G) * rowslots;
+  for (uint32_t i = threadIdx.x; i < (2u << LOG_N2); i += blockDim.x) tl[i] = T.tab[i];
+  __syncthreads();
+  const twtab_lds TL{(lds_dp)(reinterpret_cast<double *>(tl)), LOG_N2, T.e};
+  uint32_t it = blockIdx.x;
+  if (it >= total) return;  // uniform over the workgroup
+  // item -> (product, row k1 of this thread's row group)
+  const auto locate = [&](uint32_t item, const task *&tk, uint32_t &k1, bool &self) {
+    tk = tasks + (ntasks - 1 - item / per_task);
+    const uint32_t p = (item % per_task) * G + g;
+    self = p == 0;
+    k1 = role == 0 ? p : (self ? N1 / 2 : N1 - p);
+  };
+  const task *tk;
+  uint32_t k1;
+  bool self;
+  locate(it, tk, k1, self);
+  ci v[8], nx[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = gld(tk->ya, (static_cast<size_t>(k1) << LOG_N2) + j + r * M8);
+  for (;;) {
+    const uint32_t nit = it + gridDim.x;
+    const bool more = nit < total;
+    const task *ntk = tk;
+    uint32_t nk1 = k1;
+    bool nself = self;
+    if (more) {
+      locate(nit, ntk, nk1, nself);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) nx[r] = gld(ntk->ya, (static_cast<size_t>(nk1) << LOG_N2) + j + r * M8);
+    }
+    double2 *hown = hbuf + static_cast<size_t>(rg) * rowslots;
+    double2 *hpart = self ? hown : hbuf + static_cast<size_t>(rg ^ 1) * rowslots;
+    fft8_group<LOG_N2, true>(v, j, hown, 0, TL);
+    uint32_t src[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint32_t k2 = j + r * M8;
+      src[r] = k1 == 0 ? ((N2 - k2) & (N2 - 1)) : (N2 - 1 - k2);
+    }
+    double2 pr[8];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) hown[lpad(j + r * M8)] = make_double2(v[r].rn, v[r].rh);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) pr[r] = hpart[lpad(src[r])];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) hown[lpad(j + r * M8)] = make_double2(v[r].in, v[r].ih);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const double2 pi = hpart[lpad(src[r])];
+      const ci W{pr[r].x, pr[r].y, pi.y, pi.x};  // conj(Z_{-k})
+      v[r] = ci_conj(separated_product(v[r], W));
+    }
+    __syncthreads();  // the partner has read this row's buffer
+    fft8_group<LOG_N2, true>(v, j, hown, 0, TL);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = ci_conj(apply_pass_tw(v[q], T, j + q * M8, k1, log_n));
+    stores_after_loads();
+    const size_t row = static_cast<size_t>(k1) << LOG_N2;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) gst(tk->ya, row + j + q * M8, v[q]);
+    if (!more) break;
+    it = nit;
+    tk = ntk;
+    k1 = nk1;
+    self = nself;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = nx[r];
+  }
+}
+
 // Inverse columns + scale + certification.  grid = (N2 / C, tasks).
 template <int LOG_N1>
 __global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n2, int lc, int mode,
@@ -842,6 +943,7 @@ static constexpr int MAX_DYN_LDS = 131072;
 // map a run-time length to its instantiation (F is a macro taking the length).
 #define SSA_SMALL_LENGTHS(F) F(9) F(10) F(11) F(12)
 #define SSA_PASS_LENGTHS(F) F(6) F(7) F(8) F(9) F(10) F(11)
+#define SSA_ROW_PERSIST_LENGTHS(F) F(6) F(7) F(8) F(9)
 
 hipError_t set_kernel_attributes() {
   const void *ks[] = {
@@ -854,6 +956,9 @@ hipError_t set_kernel_attributes() {
       reinterpret_cast<const void *>(&k_fft_col<L>), reinterpret_cast<const void *>(&k_fft_row<L>),
       SSA_PASS_LENGTHS(SSA_K_PASS)
 #undef SSA_K_PASS
+#define SSA_K_ROWP(L) reinterpret_cast<const void *>(&k_row_pair_p<L>),
+      SSA_ROW_PERSIST_LENGTHS(SSA_K_ROWP)
+#undef SSA_K_ROWP
   };
   for (const void *k : ks) {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, MAX_DYN_LDS);
@@ -895,6 +1000,32 @@ hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bi
   return hipGetLastError();
 }
 
+// Workgroups of a kernel resident at once on the whole GPU (occupancy per CU
+// times CUs), cached per kernel and shape; at least 1.
+static uint32_t resident_workgroups(const void *kernel, int threads, size_t lds) {
+  struct entry {
+    const void *k;
+    int t;
+    size_t l;
+    uint32_t n;
+  };
+  static entry cache[64];
+  static int used = 0;
+  for (int i = 0; i < used; ++i)
+    if (cache[i].k == kernel && cache[i].t == threads && cache[i].l == lds) return cache[i].n;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    hipGetLastError();
+    per_cu = 1;
+    cus = 1;
+  }
+  const uint32_t n = static_cast<uint32_t>(std::max(1, per_cu) * std::max(1, cus));
+  if (used < 64) cache[used++] = entry{kernel, threads, lds, n};
+  return n;
+}
+
 static inline int log2_int(int x) {
   int l = 0;
   while ((1 << l) < x) ++l;
@@ -927,7 +1058,29 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (cfg.pack) {
+  if (cfg.pack && cfg.persist) {
+    const int threads = 2 * cfg.rows * static_cast<int>(N2 / 8);
+    const size_t lds = sizeof(double2) * (2 * lpad_size(N2) * cfg.rows + (size_t(2) << l2));
+    const uint32_t total = N1 / 2 / cfg.rows * static_cast<uint32_t>(ntasks);
+    mark(hk, KIND_ROW, 0);
+    switch (l2) {
+#define SSA_L(L)                                                                                  \
+  case L: {                                                                                       \
+    const uint32_t res = resident_workgroups(reinterpret_cast<const void *>(&k_row_pair_p<L>),    \
+                                             threads, lds);                                       \
+    hipLaunchKernelGGL(k_row_pair_p<L>, dim3(std::min(total, res)), dim3(threads), lds, s,        \
+                       d_tasks, ntasks, l1, cfg.rows, T);                                         \
+    break;                                                                                        \
+  }
+      SSA_ROW_PERSIST_LENGTHS(SSA_L)
+#undef SSA_L
+      default:
+        return hipErrorInvalidValue;
+    }
+    mark(hk, KIND_ROW, 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  } else if (cfg.pack) {
     const int threads = 2 * cfg.rows * static_cast<int>(N2 / 8);
     const size_t lds = sizeof(double2) * 2 * lpad_size(N2) * cfg.rows;
     const dim3 grid(N1 / 2 / cfg.rows, ntasks);

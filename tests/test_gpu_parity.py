@@ -370,7 +370,11 @@ def _valid_shapes(log_n, packed=True):
                         or rt > 512 or rt % 64 or (2 if packed else 1) * rows * pad2 * 16 > 81920
                         or ((1 << l1) // 2 if packed else (1 << l1)) % rows):
                     continue
-                out.append((l1, cols, rows))
+                out.append((l1, cols, rows, 0))
+                # the persistent row pass: packed rows of at most 2^9 points, with the
+                # twiddle levels up to 2^l2 in LDS beside the exchange buffers
+                if packed and l2 <= 9 and (2 * rows * pad2 + (2 << l2)) * 16 <= 81920:
+                    out.append((l1, cols, rows, 1))
     return out
 
 
@@ -383,16 +387,47 @@ def test_every_launch_shape_gives_the_same_product(nbytes, separate):
     want = int_product(a, b)
     shapes = _valid_shapes(log_n, packed=not separate)
     assert len(shapes) >= 4
-    for l1, cols, rows in shapes:
-        plan.set_config(log_n, l1, cols, rows)
-        assert plan.get_config(log_n) == {"log_n1": l1, "cols": cols, "rows": rows}
+    for l1, cols, rows, pers in shapes:
+        plan.set_config(log_n, l1, cols, rows, pers)
+        assert plan.get_config(log_n) == {"log_n1": l1, "cols": cols, "rows": rows,
+                                          "persistent": pers}
         st, out = plan.mul(a, b)
-        assert st == binding.SSA_OK, (l1, cols, rows)
-        assert np.array_equal(_np(out), want), (l1, cols, rows)
+        assert st == binding.SSA_OK, (l1, cols, rows, pers)
+        assert np.array_equal(_np(out), want), (l1, cols, rows, pers)
     with pytest.raises(binding.SsaError):
         plan.set_config(log_n, 3, 1, 1)
     with pytest.raises(binding.SsaError):
         plan.set_config(log_n, log_n // 2, 3, 1)
+    with pytest.raises(binding.SsaError):
+        plan.set_config(log_n, 6, 8, 1, 2)  # persistent flag out of range
+    plan.close()
+
+
+@pytest.mark.parametrize("log_n,nbytes,shape", [(18, 75000, (9, 4, 1, 1)), (18, 75000, (9, 2, 2, 1)),
+                                               (14, 5000, (7, 8, 4, 1)), (16, 30000, (7, 4, 2, 1))])
+def test_persistent_row_pass_batch(log_n, nbytes, shape):
+    """Batches long enough that every persistent row-pass workgroup walks several
+    items (prefetching the next while computing the current), products in
+    descending order: random, all-0xFF and ragged operands, all exact."""
+    plan = binding.Plan(nbytes, nbytes)
+    assert binding.fft_size(nbytes, nbytes).bit_length() - 1 == log_n
+    plan.set_config(log_n, *shape)
+    A, B = [], []
+    for i in range(40):
+        if i % 3 == 1:
+            A.append(all_ff(nbytes))
+            B.append(all_ff(nbytes - 5 * i))
+        else:
+            a, b = pair(900 + i, nbytes - 3 * i, nbytes - 7 * (i % 5))
+            A.append(a)
+            B.append(b)
+    assert all(binding.fft_size(len(a), len(b)).bit_length() - 1 == log_n for a, b in zip(A, B))
+    bt = binding.Batch(plan, A, B)
+    st = _np(bt.run())
+    assert np.all(st == binding.SSA_OK)
+    for i in range(len(A)):
+        assert np.array_equal(_np(bt.OUT[i]), int_product(A[i], B[i])), i
+    bt.close()
     plan.close()
 
 
@@ -405,7 +440,7 @@ def test_autotuner_choice_is_used_and_correct(tmp_path):
     print("autotune 2^18:", res)
     again = plan.autotune(18, count=8, cache=cache)
     assert again["cached"] and again["log_n1"] == res["log_n1"]
-    assert plan.get_config(18) == {k: res[k] for k in ("log_n1", "cols", "rows")}
+    assert plan.get_config(18) == {k: res[k] for k in ("log_n1", "cols", "rows", "persistent")}
     a, b = pair(2, n)
     st, out = plan.mul(a, b)
     assert st == binding.SSA_OK and np.array_equal(_np(out), int_product(a, b))
