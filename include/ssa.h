@@ -118,6 +118,13 @@ ssa_status ssa_mul(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b
  * Batches created afterwards use the new policy. */
 ssa_status ssa_plan_set_fp32_policy(ssa_plan *plan, int max_coeffs, int force_fail);
 
+/* Test hook for the failure path: with on = 1, certification treats every
+ * coefficient's enclosure as holding several integers, so products report
+ * SSA_ENCLOSURE_TOO_WIDE and zero-filled outputs (the carry scan writes zeros).
+ * Affects ssa_mul calls and batches created while it is on; on = 0 restores
+ * normal certification.  SSA_INVALID_ARGUMENT for another value. */
+ssa_status ssa_plan_force_too_wide(ssa_plan *plan, int on);
+
 /* Statistics of the last ssa_mul on this plan. */
 ssa_status ssa_get_stats(const ssa_plan *plan, ssa_stats *stats_host);
 

@@ -36,7 +36,7 @@ EXPORTS = ("ssa_fft_size", "ssa_plan_create", "ssa_plan_destroy", "ssa_mul", "ss
            "ssa_mul_batch", "ssa_debug_enclosures", "ssa_twiddle_table", "ssa_probe_directed",
            "ssa_batch_run_timed", "ssa_batch_kernel_times", "ssa_plan_get_config",
            "ssa_plan_set_config", "ssa_plan_autotune", "ssa_plan_set_fp32_policy",
-           "ssa_fft_forward")
+           "ssa_fft_forward", "ssa_plan_force_too_wide")
 KERNEL_KINDS = ("small", "col_fwd", "row", "col_inv", "carry", "status")
 
 
@@ -122,6 +122,8 @@ def lib():
                                         ctypes.POINTER(ctypes.c_int)]
         L.ssa_plan_set_fp32_policy.restype = ctypes.c_int
         L.ssa_plan_set_fp32_policy.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
+        L.ssa_plan_force_too_wide.restype = ctypes.c_int
+        L.ssa_plan_force_too_wide.argtypes = [_vp, ctypes.c_int]
         L.ssa_fft_forward.restype = ctypes.c_int
         L.ssa_fft_forward.argtypes = [_vp, ctypes.c_int, _sz, _vp, _vp, ctypes.POINTER(ctypes.c_int),
                                       _vp]
@@ -211,6 +213,10 @@ class Plan:
         force_fail makes every attempt fail (tests the FP64 re-run)."""
         _check(lib().ssa_plan_set_fp32_policy(self.handle, int(max_log_n), int(bool(force_fail))),
                "ssa_plan_set_fp32_policy")
+
+    def force_too_wide(self, on=True):
+        """Test hook: certification refuses every coefficient while on."""
+        _check(lib().ssa_plan_force_too_wide(self.handle, int(bool(on))), "ssa_plan_force_too_wide")
 
     def debug_enclosures(self, a, b):
         """(status, out, enclosures N x 4 float64 {re_lo, re_hi, im_lo, im_hi})."""

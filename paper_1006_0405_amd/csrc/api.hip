@@ -126,6 +126,7 @@ struct ssa_plan {
   ssa_plan_opts opts{};
   uint32_t fp32_max_L = 0;  // FP32 first attempt for products with L <= this (0: never)
   int hooks = 0;         // test hooks (HOOK_FORCE_FP32_FAIL)
+  int force_too_wide = 0;  // test hook: certification refuses every coefficient
   size_t max_na = 0, max_nb = 0;
   int log_nmax = 0;
   // twiddles
@@ -201,7 +202,8 @@ bool fp32_first(const ssa_plan *p, uint64_t L, int log_n) {
 // the first n32 of them are marked for the FP32 first attempt.
 hipError_t enqueue_class(const ssa_plan *p, const task *d_tasks, int n, int n32, int log_n,
                          double *dbg, hipStream_t s, const timing_hook *hk = nullptr) {
-  const int bits = p->opts.digit_bits, mode = p->opts.certify_mode;
+  const int bits = p->opts.digit_bits;
+  const int mode = p->force_too_wide ? CERT_FORCE_TOO_WIDE : p->opts.certify_mode;
   const int pack = p->opts.separate_transforms ? 0 : 1;
   if (log_n <= SMALL_MAX_LOG) {
     if (n32 == 0)
@@ -389,6 +391,12 @@ ssa_status ssa_plan_set_fp32_policy(ssa_plan *plan, int max_coeffs, int force_fa
     return SSA_INVALID_ARGUMENT;
   plan->fp32_max_L = static_cast<uint32_t>(max_coeffs);
   plan->hooks = force_fail ? HOOK_FORCE_FP32_FAIL : 0;
+  return SSA_OK;
+}
+
+ssa_status ssa_plan_force_too_wide(ssa_plan *plan, int on) {
+  if (!plan || (on != 0 && on != 1)) return SSA_INVALID_ARGUMENT;
+  plan->force_too_wide = on;
   return SSA_OK;
 }
 

@@ -39,7 +39,8 @@ struct task {
   uint32_t fp32;          // 1: FP32 first attempt, FP64 re-run on failure
 };
 
-enum { CERT_ONE_INTEGER = 0, CERT_HALF_INTEGER = 1 };
+// CERT_FORCE_TOO_WIDE: test hook, every coefficient counts as too wide.
+enum { CERT_ONE_INTEGER = 0, CERT_HALF_INTEGER = 1, CERT_FORCE_TOO_WIDE = 2 };
 
 // Tile of the carry scan: 4 wavefronts x 8 chunks of 64 positions (half the LDS of 16 chunks, so twice the resident tiles: 15% faster).
 static constexpr int CARRY_THREADS = 256;

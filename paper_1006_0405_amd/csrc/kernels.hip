@@ -80,7 +80,7 @@ __device__ __forceinline__ unsigned long long certify(const ci &z, uint32_t i, u
     acc.internal++;
     return 0ull;
   }
-  if (m < M || (mode == CERT_HALF_INTEGER && half)) {
+  if (m < M || (mode == CERT_HALF_INTEGER && half) || mode == CERT_FORCE_TOO_WIDE) {
     acc.too_wide++;
     return 0ull;
   }

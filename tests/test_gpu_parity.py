@@ -12,6 +12,7 @@ from fractions import Fraction
 import mpmath
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from paper_1006_0405_amd import binding
@@ -308,6 +309,56 @@ def test_strict_half_integer_mode_never_wrong():
         else:
             assert not _np(out).any()
     plan.close()
+
+
+def test_too_wide_status_zero_fills_output():
+    """The failure contract: a product whose enclosures are refused reports
+    SSA_ENCLOSURE_TOO_WIDE and an all-zero output, on the single-workgroup path,
+    the multi-pass path (carry scan) and in a batch; normal certification
+    returns afterwards."""
+    plan = binding.Plan(40000, 40000)
+    cases = [pair(31, 1000, 700), pair(32, 40000, 39000), (all_ff(20000), all_ff(20000))]
+    plan.force_too_wide(True)
+    for a, b in cases:
+        out = torch.full((len(a) + len(b),), 0xAB, dtype=torch.uint8, device="cuda")
+        st, out = plan.mul(a, b, out=out)
+        assert st == binding.SSA_ENCLOSURE_TOO_WIDE
+        assert not _np(out).any()
+        assert plan.stats()["too_wide"] > 0
+    bt = binding.Batch(plan, [c[0] for c in cases], [c[1] for c in cases])
+    for o in bt.OUT:
+        o.fill_(0xCD)
+    assert np.all(_np(bt.run()) == binding.SSA_ENCLOSURE_TOO_WIDE)
+    assert all(not _np(o).any() for o in bt.OUT)
+    bt.close()
+    plan.force_too_wide(False)
+    for a, b in cases:
+        st, out = plan.mul(a, b)
+        assert st == binding.SSA_OK and np.array_equal(_np(out), int_product(a, b))
+    rc = binding.lib().ssa_plan_force_too_wide(plan.handle, 2)
+    assert rc == binding.SSA_INVALID_ARGUMENT
+    plan.close()
+
+
+def test_largest_transform_base256():
+    """The largest transform a plan accepts (2^22) with base-256 digits: 2 MiB
+    operands (beyond the FP64 certification frontier for random bytes: the
+    enclosures are refused); certified products are exact, a refused one is all
+    zeros, and operands one byte longer are rejected at plan creation."""
+    n = 1 << 21
+    a, b = pair(77, n)
+    plan = binding.Plan(n, n)
+    st, out = plan.mul(a, b)
+    s = plan.stats()
+    print("2^22 base 256: status", st, "radius", s["max_radius"])
+    assert s["log_n"] == 22
+    if st == binding.SSA_OK:
+        assert np.array_equal(_np(out), int_product(a, b))
+    else:
+        assert st == binding.SSA_ENCLOSURE_TOO_WIDE and not _np(out).any()
+    plan.close()
+    with pytest.raises(binding.SsaError):
+        binding.Plan(n + 1, n + 1)  # L = 2^22 + 1 needs a transform of 2^23
 
 
 # ---------------------------------------------------------------------------
