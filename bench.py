@@ -277,6 +277,30 @@ def measure_singles(binding, torch, reps=10):
     return out
 
 
+def measure_reach(binding, torch):
+    """How far the FP64 rectangular-interval path certifies base-256 products of
+    two equal-length operands (uniform random bytes, seed 2, and all-0xFF):
+    status and maximum enclosure radius per length, at the lengths where the
+    transform doubles.  A certified product is checked against CPython's integer
+    product (up to 2^19 bytes per operand, to bound the host time)."""
+    from paper_1006_0405_amd.workloads import all_ff, pair
+    out = []
+    for n in (75_000, 1 << 17, 1 << 18, 1 << 19, 1 << 20, 1 << 21):
+        plan = binding.Plan(n, n)
+        for kind in ("random", "all_ff"):
+            a, b = pair(2, n) if kind == "random" else (all_ff(n), all_ff(n))
+            st, res = plan.mul(a, b)
+            s = plan.stats()
+            if st == binding.SSA_OK and n <= (1 << 19):
+                want = (int.from_bytes(a.tobytes(), "little") *
+                        int.from_bytes(b.tobytes(), "little")).to_bytes(2 * n, "little")
+                assert res.cpu().numpy().tobytes() == want, (n, kind)
+            out.append({"operand_bytes": n, "fft_length": 1 << s["log_n"], "operands": kind,
+                        "status": binding.STATUS_NAMES[st], "max_radius": s["max_radius"]})
+        plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,6 +465,7 @@ def main():
 
     if not args.no_singles:
         result["single_products"] = measure_singles(binding, torch)
+        result["fp64_reach_base256"] = measure_reach(binding, torch)
 
     if not args.no_fft:
         result["fft_forward_2p18"] = measure_fft(binding, torch, max(5, args.steps // 5))
