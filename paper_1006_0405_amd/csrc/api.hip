@@ -310,7 +310,8 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
             hip_ok(hipHostMalloc(&p->h_task, sizeof(task), hipHostMallocDefault)) &&
             hip_ok(hipHostMalloc(&p->h_stats, sizeof(dev_stats), hipHostMallocDefault));
   if (ok && log_nmax > SMALL_MAX_LOG)
-    ok = hip_ok(hipMalloc(&p->ya, sizeof(ci) * N)) && hip_ok(hipMalloc(&p->yb, sizeof(ci) * N));
+    ok = hip_ok(hipMalloc(&p->ya, sizeof(ci) * N)) &&  // the packed transform needs one array
+         (!o.separate_transforms || hip_ok(hipMalloc(&p->yb, sizeof(ci) * N)));
   if (!ok) {
     free_plan(p);
     hipGetLastError();
@@ -539,7 +540,7 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
   for (size_t i = 0; i < count; ++i) {
     const size_t N = size_t(1) << lg[i];
     if (lg[i] > SMALL_MAX_LOG) {
-      arena_elems += 2 * N;
+      arena_elems += (plan->opts.separate_transforms ? 2 : 1) * N;  // packed: one array
       c_elems += N;
       tiles += (na[i] + nb[i] + CARRY_TILE - 1) / CARRY_TILE;
     }
@@ -578,8 +579,8 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
     if (lg[i] > SMALL_MAX_LOG) {
       const size_t N = size_t(1) << lg[i];
       t.ya = bt->arena + ao;
-      t.yb = bt->arena + ao + N;
-      ao += 2 * N;
+      t.yb = plan->opts.separate_transforms ? bt->arena + ao + N : nullptr;
+      ao += (plan->opts.separate_transforms ? 2 : 1) * N;
       t.c = bt->carena + co;
       co += N;
       t.ntiles = static_cast<uint32_t>((na[i] + nb[i] + CARRY_TILE - 1) / CARRY_TILE);
