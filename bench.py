@@ -298,6 +298,16 @@ def measure_reach(binding, torch):
             out.append({"operand_bytes": n, "fft_length": 1 << s["log_n"], "operands": kind,
                         "status": binding.STATUS_NAMES[st], "max_radius": s["max_radius"]})
         plan.close()
+    # the refused random product once more with base-16 refinement
+    n = 1 << 20
+    plan = binding.Plan(n, n, refine_digits=True)
+    a, b = pair(2, n)
+    st, res = plan.mul(a, b)
+    s = plan.stats()
+    out.append({"operand_bytes": n, "fft_length": 1 << s["log_n"], "operands": "random",
+                "refine_digits": True, "refined": s["refined"],
+                "status": binding.STATUS_NAMES[st], "max_radius": s["max_radius"]})
+    plan.close()
     return out
 
 

@@ -67,6 +67,13 @@ typedef struct {
                               (A_k = (Z_k + conj Z_{-k})/2, B_k = (Z_k - conj Z_{-k})/2i);
                               1: one forward FFT per operand, as in the fast
                               convolution box of section 2.3.  Same products.       */
+  int refine_digits;       /* 0 (default) or 1 with digit_bits = 8: ssa_mul re-runs a
+                              product whose enclosures hold several integers with
+                              base-16 digits (coefficients 289 times smaller, a
+                              transform twice as long) when that transform is at most
+                              2^22 points; the plan allocates for it.  The product is
+                              the same; stats.refined says which run produced it.
+                              Batches report the base-256 outcome.                 */
 } ssa_plan_opts;
 
 typedef struct {
@@ -80,7 +87,8 @@ typedef struct {
   int fallback;        /* 1: the FP32 attempt failed and the FP64 re-run produced the
                           result (SSA_FP32_FALLBACK plans only)                         */
   int fp32_attempt;    /* 1: the product went through an FP32 attempt                  */
-  int reserved;
+  int refined;         /* 1: base 256 was too wide and the base-16 re-run produced it
+                          (plans with refine_digits)                                  */
 } ssa_stats;
 
 typedef struct ssa_plan ssa_plan;
@@ -211,13 +219,15 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
 
 /* Same computation as ssa_mul, and also writes the final enclosures of all N
  * convolution outputs (after the inverse transform and the 1/N factor, before
- * certification) to enc_dev: N x 4 doubles {re_lo, re_hi, im_lo, im_hi}. */
+ * certification) to enc_dev: N x 4 doubles {re_lo, re_hi, im_lo, im_hi}, with N
+ * the transform length of the plan's own digit size (no base-16 refinement). */
 ssa_status ssa_debug_enclosures(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b,
                                 size_t nb, uint8_t *out, double *enc_dev, ssa_status *status);
 
 /* Copy the plan's twiddle table: Ntab x 2 doubles (cos, sin of 2 pi t / Ntab)
  * to tab_dev, and its common error bound to *e_host.  Returns log2(Ntab) in
- * *log_ntab_host. */
+ * *log_ntab_host.  Ntab is the longest transform the plan allocates for: that of
+ * max_na x max_nb in its digit size, or the base-16 one with refine_digits. */
 ssa_status ssa_twiddle_table(const ssa_plan *plan, double *tab_dev, double *e_host,
                              int *log_ntab_host);
 

@@ -46,7 +46,8 @@ class SsaError(RuntimeError):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("digit_bits", ctypes.c_int),
-                ("certify_mode", ctypes.c_int), ("separate_transforms", ctypes.c_int)]
+                ("certify_mode", ctypes.c_int), ("separate_transforms", ctypes.c_int),
+                ("refine_digits", ctypes.c_int)]
 
 
 class LaunchConfig(ctypes.Structure):
@@ -63,10 +64,10 @@ class Stats(ctypes.Structure):
                 ("too_wide", ctypes.c_uint32), ("internal", ctypes.c_uint32),
                 ("carry_err", ctypes.c_uint32), ("log_n", ctypes.c_uint32),
                 ("status", ctypes.c_int), ("fallback", ctypes.c_int),
-                ("fp32_attempt", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("fp32_attempt", ctypes.c_int), ("refined", ctypes.c_int)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -163,7 +164,8 @@ class Plan:
     """A plan for products with at most max_na x max_nb bytes."""
 
     def __init__(self, max_na, max_nb, digit_bits=8, certify_mode=SSA_CERTIFY_ONE_INTEGER,
-                 separate_transforms=False, precision="fp64", stream=None, device=None):
+                 separate_transforms=False, precision="fp64", stream=None, device=None,
+                 refine_digits=False):
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.digit_bits = digit_bits
@@ -172,13 +174,14 @@ class Plan:
             raise SsaError("precision %r is not available (one of %s)" % (precision, sorted(PRECISIONS)))
         self.precision = precision
         opts = PlanOpts(PRECISIONS[precision], digit_bits, certify_mode,
-                        int(bool(separate_transforms)))
+                        int(bool(separate_transforms)), int(bool(refine_digits)))
         h = _vp()
         with torch.cuda.device(self.device):
             _check(lib().ssa_plan_create(ctypes.byref(h), max_na, max_nb, ctypes.byref(opts),
                                          _vp(self.stream.cuda_stream)), "ssa_plan_create")
         self.handle = h
         self.max_na, self.max_nb = max_na, max_nb
+        self.refine_digits = bool(refine_digits)
 
     def close(self):
         if self.handle:
@@ -296,6 +299,8 @@ class Plan:
     def twiddles(self):
         """(table Ntab x 2 float64 device tensor, error bound e, log2 Ntab)."""
         n = fft_size(self.max_na, self.max_nb, self.digit_bits)
+        if self.refine_digits:  # the plan also holds the base-16 transform (at most 2^22)
+            n = max(n, min(fft_size(self.max_na, self.max_nb, 4), 1 << 22))
         tab = torch.empty((n, 2), dtype=torch.float64, device=self.device)
         e = ctypes.c_double(0)
         lg = ctypes.c_int(0)

@@ -109,6 +109,7 @@ ssa_stats to_public(const dev_stats &s, int log_n) {
   o.status = status_from(s);
   o.fallback = static_cast<int>(s.fallback);
   o.fp32_attempt = static_cast<int>(s.fp32);
+  o.refined = 0;
   return o;
 }
 
@@ -129,6 +130,7 @@ struct ssa_plan {
   int force_too_wide = 0;  // test hook: certification refuses every coefficient
   size_t max_na = 0, max_nb = 0;
   int log_nmax = 0;
+  int log_nref = 0;  // refine_digits: largest base-16 re-run transform (0: none)
   // twiddles
   double2 *tab = nullptr;
   int log_ntab = 0;
@@ -201,8 +203,9 @@ bool fp32_first(const ssa_plan *p, uint64_t L, int log_n) {
 // Enqueue one product class: all tasks [d_tasks, d_tasks + n) share log_n, and
 // the first n32 of them are marked for the FP32 first attempt.
 hipError_t enqueue_class(const ssa_plan *p, const task *d_tasks, int n, int n32, int log_n,
-                         double *dbg, hipStream_t s, const timing_hook *hk = nullptr) {
-  const int bits = p->opts.digit_bits;
+                         double *dbg, hipStream_t s, const timing_hook *hk = nullptr,
+                         int bits = 0) {
+  if (bits == 0) bits = p->opts.digit_bits;
   const int mode = p->force_too_wide ? CERT_FORCE_TOO_WIDE : p->opts.certify_mode;
   const int pack = p->opts.separate_transforms ? 0 : 1;
   if (log_n <= SMALL_MAX_LOG) {
@@ -217,12 +220,9 @@ hipError_t enqueue_class(const ssa_plan *p, const task *d_tasks, int n, int n32,
   return launch_multipass(d_tasks, n, log_n, p->cfg[log_n], bits, mode, tw_of(p), dbg, s, hk);
 }
 
-ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
-                      uint8_t *out, double *dbg, ssa_status *status) {
-  if (!p || !a || !b || !out || !status || na == 0 || nb == 0 || na > p->max_na ||
-      nb > p->max_nb)
-    return SSA_INVALID_ARGUMENT;
-  const int bits = p->opts.digit_bits;
+// One product with the given digit size; the FP32 attempt only in the plan's own.
+ssa_status run_once(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
+                    uint8_t *out, double *dbg, ssa_status *status, int bits) {
   const uint64_t nda = digits(na, bits), ndb = digits(nb, bits);
   const uint64_t L = nda + ndb - 1;
   const int log_n = log_n_for(L);
@@ -243,11 +243,12 @@ ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b
   t.st = p->st;
   t.tiles = p->tiles;
   t.ntiles = static_cast<uint32_t>((na + nb + CARRY_TILE - 1) / CARRY_TILE);
-  t.fp32 = fp32_first(p, L, log_n) ? 1u : 0u;
+  t.fp32 = (bits == p->opts.digit_bits && fp32_first(p, L, log_n)) ? 1u : 0u;
   hipStream_t s = p->stream;
   if (!hip_ok(hipMemcpyAsync(p->d_task, p->h_task, sizeof(task), hipMemcpyHostToDevice, s)))
     return SSA_DEVICE_ERROR;
-  if (!hip_ok(enqueue_class(p, p->d_task, 1, static_cast<int>(t.fp32), log_n, dbg, s)))
+  if (!hip_ok(enqueue_class(p, p->d_task, 1, static_cast<int>(t.fp32), log_n, dbg, s, nullptr,
+                            bits)))
     return SSA_DEVICE_ERROR;
   if (log_n > SMALL_MAX_LOG && !hip_ok(launch_carry(p->d_task, 1, t.ntiles, bits, s)))
     return SSA_DEVICE_ERROR;
@@ -257,6 +258,22 @@ ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b
   p->last = to_public(*p->h_stats, log_n);
   *status = static_cast<ssa_status>(p->last.status);
   return SSA_OK;
+}
+
+ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
+                      uint8_t *out, double *dbg, ssa_status *status) {
+  if (!p || !a || !b || !out || !status || na == 0 || nb == 0 || na > p->max_na ||
+      nb > p->max_nb)
+    return SSA_INVALID_ARGUMENT;
+  ssa_status r = run_once(p, a, na, b, nb, out, dbg, status, p->opts.digit_bits);
+  // refinement: a base-256 product whose enclosures are too wide, again in base 16
+  // (not for ssa_debug_enclosures: its buffer holds the base-256 transform only)
+  if (r == SSA_OK && *status == SSA_ENCLOSURE_TOO_WIDE && p->opts.refine_digits && !dbg &&
+      log_n_for(digits(na, 4) + digits(nb, 4) - 1) <= p->log_nref) {
+    r = run_once(p, a, na, b, nb, out, dbg, status, 4);
+    p->last.refined = 1;
+  }
+  return r;
 }
 
 }  // namespace
@@ -277,11 +294,16 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
   if (max_na == 0 || max_nb == 0 || (o.digit_bits != 8 && o.digit_bits != 4) ||
       (o.certify_mode != SSA_CERTIFY_ONE_INTEGER && o.certify_mode != SSA_CERTIFY_HALF_INTEGER) ||
       (o.precision != SSA_FP64 && o.precision != SSA_FP32_FALLBACK) ||
-      (o.separate_transforms != 0 && o.separate_transforms != 1))
+      (o.separate_transforms != 0 && o.separate_transforms != 1) ||
+      (o.refine_digits != 0 && (o.refine_digits != 1 || o.digit_bits != 8)))
     return SSA_INVALID_ARGUMENT;
   const uint64_t L = digits(max_na, o.digit_bits) + digits(max_nb, o.digit_bits) - 1;
   const int log_nmax = log_n_for(L);
   if (log_nmax > MAX_LOG_N) return SSA_INVALID_ARGUMENT;
+  // the base-16 re-run of refine_digits, as far as a transform of 2^MAX_LOG_N reaches
+  const int log_nref =
+      o.refine_digits ? std::min(log_n_for(digits(max_na, 4) + digits(max_nb, 4) - 1), MAX_LOG_N) : 0;
+  const int log_nalloc = std::max(log_nmax, log_nref);
   if (!kernels_configured) {
     if (!hip_ok(set_kernel_attributes())) return SSA_DEVICE_ERROR;
     kernels_configured = true;
@@ -295,10 +317,11 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
   p->max_na = max_na;
   p->max_nb = max_nb;
   p->log_nmax = log_nmax;
-  p->log_ntab = log_nmax;
+  p->log_nref = log_nref;
+  p->log_ntab = log_nalloc;
   for (int l = SMALL_MAX_LOG + 1; l <= MAX_LOG_N; ++l)
     p->cfg[l] = default_cfg(l, o.separate_transforms ? 0 : 1);
-  const size_t N = size_t(1) << log_nmax;
+  const size_t N = size_t(1) << log_nalloc;
   const size_t ntiles = (max_na + max_nb + CARRY_TILE - 1) / CARRY_TILE;
   bool ok = hip_ok(hipMalloc(&p->tab, sizeof(double2) << (p->log_ntab + 1))) &&  // level tables
             hip_ok(hipMalloc(&p->ebits, sizeof(unsigned long long))) &&
@@ -309,7 +332,7 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
             hip_ok(hipMalloc(&p->d_task, sizeof(task))) &&
             hip_ok(hipHostMalloc(&p->h_task, sizeof(task), hipHostMallocDefault)) &&
             hip_ok(hipHostMalloc(&p->h_stats, sizeof(dev_stats), hipHostMallocDefault));
-  if (ok && log_nmax > SMALL_MAX_LOG)
+  if (ok && log_nalloc > SMALL_MAX_LOG)
     ok = hip_ok(hipMalloc(&p->ya, sizeof(ci) * N)) &&  // the packed transform needs one array
          (!o.separate_transforms || hip_ok(hipMalloc(&p->yb, sizeof(ci) * N)));
   if (!ok) {

@@ -340,6 +340,37 @@ def test_too_wide_status_zero_fills_output():
     plan.close()
 
 
+@pytest.mark.parametrize("n", [1 << 20])
+def test_refine_digits_rescues_base256(n):
+    """A random base-256 product beyond the FP64 frontier (1 MiB operands,
+    N = 2^21) is refused in base 256; a plan with refine_digits re-runs it with
+    base-16 digits (N = 2^22) and returns the exact product.  A product that
+    certifies in base 256 is not re-run; with every enclosure refused both runs
+    fail and the output is all zeros."""
+    a, b = pair(2, n)
+    plain = binding.Plan(n, n)
+    st, _ = plain.mul(a, b)
+    assert st == binding.SSA_ENCLOSURE_TOO_WIDE and plain.stats()["refined"] == 0
+    plain.close()
+    plan = binding.Plan(n, n, refine_digits=True)
+    st, out = plan.mul(a, b)
+    s = plan.stats()
+    print("refined:", s)
+    assert st == binding.SSA_OK and s["refined"] == 1 and s["log_n"] == 22
+    assert np.array_equal(_np(out), int_product(a, b))
+    c, d = pair(3, 70000)
+    st, out = plan.mul(c, d)
+    assert st == binding.SSA_OK and plan.stats()["refined"] == 0
+    assert np.array_equal(_np(out), int_product(c, d))
+    plan.force_too_wide(True)
+    st, out = plan.mul(c, d)
+    assert st == binding.SSA_ENCLOSURE_TOO_WIDE and plan.stats()["refined"] == 1
+    assert not _np(out).any()
+    plan.close()
+    with pytest.raises(binding.SsaError):
+        binding.Plan(100, 100, digit_bits=4, refine_digits=True)
+
+
 def test_largest_transform_base256():
     """The largest transform a plan accepts (2^22) with base-256 digits: 2 MiB
     operands (beyond the FP64 certification frontier for random bytes: the
