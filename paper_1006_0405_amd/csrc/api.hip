@@ -128,6 +128,7 @@ struct ssa_plan {
   uint32_t fp32_max_L = 0;  // FP32 first attempt for products with L <= this (0: never)
   int hooks = 0;         // test hooks (HOOK_FORCE_FP32_FAIL)
   int force_too_wide = 0;  // test hook: certification refuses every coefficient
+  int split_graph = 1;     // batch graphs run each multi-pass class as two concurrent halves
   size_t max_na = 0, max_nb = 0;
   int log_nmax = 0;
   int log_nref = 0;  // refine_digits: largest base-16 re-run transform (0: none)
@@ -485,11 +486,23 @@ namespace {
 
 // Per length class one launch (or three), then one carry scan over every
 // multi-pass product, then the statuses.
-hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk) {
+// side (graph capture only): a second stream; each multi-pass class is then
+// split in two halves, the second half launched on `side` between a fork and a
+// join event, so that the two halves' kernels can share the GPU (one half's
+// memory phases overlap the other's arithmetic).
+hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk,
+                         hipStream_t side = nullptr, hipEvent_t fork = nullptr,
+                         hipEvent_t join = nullptr) {
   const ssa_plan *p = bt->plan;
   const int bits = p->opts.digit_bits;
   size_t s0 = 0;
   const size_t count = bt->count;
+  const bool split = side != nullptr && bt->n_multi >= 2;
+  if (split) {
+    hipError_t e = hipEventRecord(fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    if (e != hipSuccess) return e;
+  }
   while (s0 < count) {
     size_t s1 = s0;
     const int l = static_cast<int>(bt->h_tasks[s0].log_n);
@@ -497,9 +510,21 @@ hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk) {
     const int n = static_cast<int>(s1 - s0);
     int n32 = 0;
     while (n32 < n && bt->h_tasks[s0 + n32].fp32) ++n32;  // marked tasks lead their class
-    const hipError_t e = enqueue_class(p, bt->d_tasks + s0, n, n32, l, nullptr, s, hk);
-    if (e != hipSuccess) return e;
+    if (split && l > SMALL_MAX_LOG && n >= 2) {
+      const int h = n / 2;
+      hipError_t e = enqueue_class(p, bt->d_tasks + s0, h, 0, l, nullptr, s, hk);
+      if (e == hipSuccess) e = enqueue_class(p, bt->d_tasks + s0 + h, n - h, 0, l, nullptr, side, hk);
+      if (e != hipSuccess) return e;
+    } else {
+      const hipError_t e = enqueue_class(p, bt->d_tasks + s0, n, n32, l, nullptr, s, hk);
+      if (e != hipSuccess) return e;
+    }
     s0 = s1;
+  }
+  if (split) {
+    hipError_t e = hipEventRecord(join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+    if (e != hipSuccess) return e;
   }
   if (bt->n_multi) {
     hipError_t e = launch_carry(bt->d_tasks, static_cast<int>(bt->n_multi), bt->max_tiles, bits, s, hk);
@@ -627,10 +652,14 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
       bt->max_tiles = std::max(bt->max_tiles, bt->h_tasks[k].ntiles);
     }
   // Capture the launch sequence into one graph.
-  hipStream_t cs = nullptr;
-  ok = hip_ok(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipStream_t cs = nullptr, side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  ok = hip_ok(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) &&
+       hip_ok(hipStreamCreateWithFlags(&side, hipStreamNonBlocking)) &&
+       hip_ok(hipEventCreateWithFlags(&fork, hipEventDisableTiming)) &&
+       hip_ok(hipEventCreateWithFlags(&join, hipEventDisableTiming));
   if (ok) ok = hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  if (ok) ok = hip_ok(enqueue_batch(bt, cs, nullptr));
+  if (ok) ok = hip_ok(enqueue_batch(bt, cs, nullptr, plan->split_graph ? side : nullptr, fork, join));
   hipGraph_t g = nullptr;
   if (cs) {
     const hipError_t ec = hipStreamEndCapture(cs, &g);
@@ -643,6 +672,9 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
     hipGraphDestroy(g);
   }
   if (cs) hipStreamDestroy(cs);
+  if (side) hipStreamDestroy(side);
+  if (fork) hipEventDestroy(fork);
+  if (join) hipEventDestroy(join);
   if (!ok) {
     ssa_batch_destroy(bt);
     hipGetLastError();
