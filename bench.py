@@ -45,12 +45,14 @@ def kernel_source_hash():
 def alg_bytes_per_product(kind, N, L, nbytes_total, packed=True):
     """Algorithmic HBM bytes one product needs in each kernel: every FP64
     interval array element read or written once is 32 bytes.  Packed: one
-    transformed array (a + i b); separate: one array per operand."""
+    transformed array (a + i b); separate: one array per operand.
+    The inverse is the half-length one of the real coefficients: N/2 elements
+    go from the row pass to the inverse column pass."""
     arrays = 1 if packed else 2
     return {
         "col_fwd": arrays * N * ELEM + nbytes_total,   # read digits, write the column-transformed array(s)
-        "row": (arrays + 1) * N * ELEM,                # read the array(s), write the inverse-half result
-        "col_inv": N * ELEM + 8 * L,                   # read it, write the certified int64 coefficients
+        "row": arrays * N * ELEM + N // 2 * ELEM,      # read the array(s), write the half-length inverse's rows
+        "col_inv": N // 2 * ELEM + 8 * L,              # read those, write the certified int64 coefficients
         "carry": 8 * L + nbytes_total,                 # read coefficients, write the product bytes
     }[kind]
 

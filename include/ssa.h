@@ -220,7 +220,9 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
 /* Same computation as ssa_mul, and also writes the final enclosures of all N
  * convolution outputs (after the inverse transform and the 1/N factor, before
  * certification) to enc_dev: N x 4 doubles {re_lo, re_hi, im_lo, im_hi}, with N
- * the transform length of the plan's own digit size (no base-16 refinement). */
+ * the transform length of the plan's own digit size (no base-16 refinement).
+ * Lengths above 2^12 run the half-length inverse of the real coefficients, whose
+ * enclosures are real: there im_lo = im_hi = 0. */
 ssa_status ssa_debug_enclosures(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b,
                                 size_t nb, uint8_t *out, double *enc_dev, ssa_status *status);
 

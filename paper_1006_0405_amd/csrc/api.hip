@@ -59,7 +59,7 @@ bool cfg_valid(const launch_cfg &c, int log_n) {
   if (c.log_n2 != log_n - c.log_n1) return false;
   const int N1 = 1 << c.log_n1, N2 = 1 << c.log_n2;
   const auto pow2 = [](int x) { return x > 0 && (x & (x - 1)) == 0; };
-  if (!pow2(c.cols) || N2 % c.cols) return false;
+  if (!pow2(c.cols) || (N2 / 2) % c.cols) return false;  // inverse columns: N2/2 of them
   const int ct = c.cols * N1 / 8;
   if (ct > 512 || ct % 64) return false;
   if ((N1 + N1 / 8) * static_cast<size_t>(c.cols) * 16 > 81920) return false;

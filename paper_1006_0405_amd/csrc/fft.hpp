@@ -21,6 +21,7 @@ __device__ __forceinline__ ci lds_get(const ci *lds, int idx) {
 // compiler emits global (not flat) loads and stores for pointers that came out
 // of a descriptor in memory.
 typedef double d2v __attribute__((ext_vector_type(2)));
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) const d2v *gcd2;
 typedef __attribute__((address_space(1))) d2v *gd2;
 __device__ __forceinline__ ci gld(const ci *g, size_t idx) {

@@ -183,4 +183,70 @@ __device__ __forceinline__ void fft8_group(ci v[8], int j, double2 *h, int lis, 
   }
 }
 
+// Exchange of 4 values per thread (M = 4 M4 elements): write result q to
+// position wpos(q), read back x[j + r M4]; two 16-byte rounds, padded slots.
+template <bool WAVE, class W>
+__device__ __forceinline__ void exchange4(ci v[4], int j, int M4, double2 *h, W wpos) {
+  double2 t[4];
+  xsync<WAVE>();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) hput(h, lpad(wpos(q)), v[q].rn, v[q].rh);
+  xsync<WAVE>();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) t[r] = h[lpad(j + r * M4)];
+  xsync<WAVE>();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) hput(h, lpad(wpos(q)), v[q].in, v[q].ih);
+  xsync<WAVE>();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double2 u = h[lpad(j + r * M4)];
+    v[r] = ci{t[r].x, t[r].y, u.x, u.y};
+  }
+}
+
+// Forward interval DFT of M = 2^LOGM elements held 4 per thread by M/4
+// threads: thread j holds x[j + r M/4], r < 4, and ends with X[j + q M/4].
+// Stockham radix-4 stages (one radix-2 stage first when LOGM is odd), same
+// conventions as fft8_group; the twiddles omega_{4 Ns}^{r k}, k < Ns, lie in
+// the first quadrant for r = 1, the upper half plane for r = 2.
+template <int LOGM, bool WAVE, class TT = twtab>
+__device__ __forceinline__ void fft4_group(ci v[4], int j, double2 *h, const TT &T) {
+  static_assert(LOGM >= 2, "length-4 groups at least");
+  constexpr int M4 = 1 << (LOGM - 2);
+  constexpr int FIRST = LOGM % 2;
+  constexpr int NR4 = (LOGM - FIRST) / 2;
+  if (FIRST == 1) {
+    // radix 2 (Ns = 1): positions jv = j + t M/4 (t < 2) pair x[jv] = v_t with
+    // x[jv + M/2] = v_{t+2}; results to y[2 jv], y[2 jv + 1]
+    ci y[4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      y[2 * t] = ci_add(v[t], v[t + 2]);
+      y[2 * t + 1] = ci_sub(v[t], v[t + 2]);
+    }
+    exchange4<WAVE>(y, j, M4, h, [&](int q) { return 2 * (j + (q >> 1) * M4) + (q & 1); });
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = y[r];
+  }
+#pragma unroll
+  for (int st = 0; st < NR4; ++st) {
+    const int logNs = FIRST + 2 * st;
+    const int Ns = 1 << logNs;
+    const int k = j & (Ns - 1);
+    if (logNs > 0) {
+      const double2 w1 = root(T, logNs + 2, static_cast<uint32_t>(k));
+      const double2 w2 = root(T, logNs + 2, static_cast<uint32_t>(2 * k));
+      const double2 w3 = root(T, logNs + 2, static_cast<uint32_t>(3 * k));
+      v[1] = ci_twiddle_q1(v[1], w1.x, w1.y, T.e);
+      v[2] = ci_twiddle_uh(v[2], w2.x, w2.y, T.e);
+      v[3] = ci_twiddle(v[3], w3.x, w3.y, T.e);
+    }
+    radix4(v);
+    if (st + 1 == NR4) break;  // X[j + q M/4] = v[q]
+    const int base = ((j - k) << 2) + k;
+    exchange4<WAVE>(v, j, M4, h, [&](int q) { return base + q * Ns; });
+  }
+}
+
 }  // namespace ssa

@@ -11,9 +11,13 @@
 //    k_col_fwd : length-N1 column DFTs of both operands, twiddle omega_N^{n2 k1},
 //                rows k1 stored contiguously;
 //    k_row     : per row k1 the length-N2 DFTs of both operands, the pointwise
-//                product, and the first half of the inverse (length-N2 DFT of the
-//                conjugate, conjugate twiddle) -- the spectrum never leaves the chip;
-//    k_col_inv : length-N1 inverse column DFTs, the 1/N scale, certification;
+//                product, and the first half of the inverse -- the spectrum never
+//                leaves the chip.  The coefficients are real, so the inverse is
+//                the half-length one of x_{2m} + i x_{2m+1} (half_inverse_input):
+//                the row DFT of the conjugate is N2/2 long and only N2/2 values
+//                per row go back to memory;
+//    k_col_inv : length-N1 inverse column DFTs over the N2/2 remaining columns,
+//                the 1/N scale, certification of both parts;
 //    k_carry   : carries as a generate/propagate scan with decoupled look-back.
 // The inverse DFT is computed as conj(DFT(conj(.)))/N, so a single forward
 // interval DFT serves every transform; conjugation is exact.
@@ -56,24 +60,23 @@ struct cert_acc {
 
 static constexpr double TWO52 = 4503599627370496.0;
 
-// For i < L the real part [lo, hi] must hold exactly one integer:
-// ceil(lo) == floor(hi) (with lo = -rn, ceil(lo) = -floor(rn)).  Several
-// integers: too wide.  No integer, a negative one, or an imaginary part that
-// excludes 0: impossible for a rigorous enclosure, counted as internal.  The
-// padded tail i >= L must contain 0 in both parts.
-__device__ __forceinline__ unsigned long long certify(const ci &z, uint32_t i, uint32_t L,
-                                                      int mode, cert_acc &acc) {
+// For i < L the real enclosure [lo, hi] = [-n, h] of coefficient i must hold
+// exactly one integer: ceil(lo) == floor(hi) (ceil(lo) = -floor(n)).  Several
+// integers: too wide.  No integer, a negative one, or (im0 false) an imaginary
+// part that excludes 0: impossible for a rigorous enclosure, counted as
+// internal.  The padded tail i >= L must contain 0.
+__device__ __forceinline__ unsigned long long certify_re(double n, double h, bool im0, uint32_t i,
+                                                         uint32_t L, int mode, cert_acc &acc) {
   if (i >= L) {
-    if (!(z.rn >= 0.0 && z.rh >= 0.0 && z.in >= 0.0 && z.ih >= 0.0)) acc.internal++;
+    if (!(n >= 0.0 && h >= 0.0 && im0)) acc.internal++;
     return 0ull;
   }
-  const double rad = ru_mul(ru_add(z.rn, z.rh), 0.5);
+  const double rad = ru_mul(ru_add(n, h), 0.5);
   acc.rad = rad > acc.rad ? rad : acc.rad;
-  const double m = -dfloor(z.rn);  // ceil(lo)
-  const double M = dfloor(z.rh);   // floor(hi)
-  const bool im0 = z.in >= 0.0 && z.ih >= 0.0;
-  const double h_lo = -dfloor(ru_add(z.rn, 0.5));  // ceil(lo - 1/2)
-  const double h_hi = dfloor(ru_add(z.rh, -0.5));  // floor(hi - 1/2)
+  const double m = -dfloor(n);  // ceil(lo)
+  const double M = dfloor(h);   // floor(hi)
+  const double h_lo = -dfloor(ru_add(n, 0.5));  // ceil(lo - 1/2)
+  const double h_hi = dfloor(ru_add(h, -0.5));  // floor(hi - 1/2)
   const bool half = h_lo <= h_hi;
   if (half) acc.half++;
   if (!(m <= M) || !im0) {
@@ -91,6 +94,11 @@ __device__ __forceinline__ unsigned long long certify(const ci &z, uint32_t i, u
   // m is an integer in [0, 2^52): m + 2^52 is exact and its low mantissa bits are m.
   const double t = ru_add(m, TWO52);
   return static_cast<unsigned long long>(__double_as_longlong(t)) - 0x4330000000000000ull;
+}
+// A complex enclosure of a real coefficient: the imaginary part must contain 0.
+__device__ __forceinline__ unsigned long long certify(const ci &z, uint32_t i, uint32_t L,
+                                                      int mode, cert_acc &acc) {
+  return certify_re(z.rn, z.rh, z.in >= 0.0 && z.ih >= 0.0, i, L, mode, acc);
 }
 
 __device__ __forceinline__ void dbg_store(double *dbg, uint32_t i, const ci &z) {
@@ -419,6 +427,46 @@ __device__ __forceinline__ ci apply_pass_tw(const ci &v, const twtab &T, uint32_
 // each interleaved pair would cost a full memory round trip.
 __device__ __forceinline__ void stores_after_loads() { __builtin_amdgcn_sched_barrier(0); }
 
+// Half-length inverse of a spectrum Z whose inverse transform x is real (the
+// product's coefficients): y_m = x_{2m} + i x_{2m+1}, m < N/2, is the
+// length-N/2 inverse DFT of
+//   U_k = (Z_k + Z_{k+N/2}) + i omega_N^{-k} (Z_k - Z_{k+N/2}),   k < N/2,
+// scaled by 1/N (split the inverse sum over even and odd n).  The inverse runs
+// as the forward DFT of the conjugate, so the rows work on P = conj Z_k and
+// Q = conj Z_{k+N/2}:  conj U_k = (P + Q) - i omega_N^k (P - Q).  An enclosure
+// of y is one of x: its real part encloses x_{2m} and its imaginary part
+// x_{2m+1}, because the exact x is real.
+__device__ __forceinline__ ci half_inverse_input(const ci &P, const ci &Q, const twtab &T,
+                                                 uint32_t k, int log_n) {
+  const ci t = apply_pass_tw(ci_sub(P, Q), T, k, 1u, log_n);
+  return ci_add(ci_add(P, Q), ci_mul_negi(t));
+}
+
+// Row k1 of the half-length inverse: v[r] holds P at k2 = j + r N2/8 (r < 8),
+// so that Z_{k+N/2} (k2 + N2/2, same row) sits in the same thread (r + 4).
+// Forms conj U for k2 < N2/2, runs the length-N2/2 row DFT and the conjugate
+// inter-pass twiddle of the length-N/2 four-step inverse, omega_{N/2}^{n2 k1},
+// and stores the N2/2 results at the start of the row.  `h` is the row's
+// exchange buffer (N2/2 elements), TF the table the row DFT reads.
+template <int LOG_N2, bool WAVE, class TT>
+__device__ __forceinline__ void half_inverse_row(const ci v[8], int j, uint32_t k1, int log_n1,
+                                                 double2 *h, const TT &TF, const twtab &T, ci *Y) {
+  constexpr int M8 = 1 << (LOG_N2 - 3);
+  const int log_n = log_n1 + LOG_N2;
+  ci u[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    u[r] = half_inverse_input(v[r], v[r + 4], T, k1 + (static_cast<uint32_t>(j + r * M8) << log_n1),
+                              log_n);
+  fft4_group<LOG_N2 - 1, WAVE>(u, j, h, TF);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) u[q] = ci_conj(apply_pass_tw(u[q], T, j + q * M8, k1, log_n - 1));
+  stores_after_loads();
+  const size_t row = static_cast<size_t>(k1) << LOG_N2;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) gst(Y, row + j + q * M8, u[q]);
+}
+
 // Statistics and carry-scan state of a product are reset by its first pass.
 __device__ __forceinline__ void reset_product_state(const task &tk) {
   if (threadIdx.x == 0) {
@@ -499,12 +547,7 @@ __device__ __forceinline__ void row_body(const task &tk, int log_n1, int R, cons
   fft8_group<LOG_N2, WAVE>(vb, j, hg, 0, T);
 #pragma unroll
   for (int r = 0; r < 8; ++r) va[r] = ci_conj(ci_mul_fast(va[r], vb[r]));
-  fft8_group<LOG_N2, WAVE>(va, j, hg, 0, T);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) va[q] = ci_conj(apply_pass_tw(va[q], T, j + q * M8, k1, log_n));
-  stores_after_loads();
-#pragma unroll
-  for (int q = 0; q < 8; ++q) gst(tk.ya, row + j + q * M8, va[q]);
+  half_inverse_row<LOG_N2, WAVE>(va, j, k1, log_n1, hg, T, T, tk.ya);
 }
 
 template <int LOG_N2>
@@ -522,8 +565,8 @@ __global__ __launch_bounds__(512) void k_row(const task *tasks, int log_n1, int 
 // the other row (pair p >= 1, rows p and N1 - p), and rows 0 and N1/2 are their
 // own partners (pair 0).  A workgroup holds G pairs, each as two row groups of
 // N2/8 threads.  Per row: forward length-N2 DFT, separated pointwise product
-// with the partner row, length-N2 DFT of the conjugate, conjugate inter-pass
-// twiddle.  grid = (N1 / 2 / G, tasks).
+// with the partner row, then the row step of the half-length inverse
+// (half_inverse_row).  grid = (N1 / 2 / G, tasks).
 template <int LOG_N2, bool WAVE>
 __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G, const twtab &T,
                                               double2 *hbuf) {
@@ -571,12 +614,7 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
     v[r] = ci_conj(separated_product(v[r], W));
   }
   __syncthreads();  // the partner has read this row's buffer
-  fft8_group<LOG_N2, WAVE, true>(v, j, hown, 0, T);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) v[q] = ci_conj(apply_pass_tw(v[q], T, j + q * M8, k1, log_n));
-  stores_after_loads();
-#pragma unroll
-  for (int q = 0; q < 8; ++q) gst(tk.ya, row + j + q * M8, v[q]);
+  half_inverse_row<LOG_N2, WAVE>(v, j, k1, log_n1, hown, T, T, tk.ya);
 }
 
 template <int LOG_N2>
@@ -672,13 +710,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
       v[r] = ci_conj(separated_product(v[r], W));
     }
     __syncthreads();  // the partner has read this row's buffer
-    fft8_group<LOG_N2, true>(v, j, hown, 0, TL);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = ci_conj(apply_pass_tw(v[q], T, j + q * M8, k1, log_n));
-    stores_after_loads();
-    const size_t row = static_cast<size_t>(k1) << LOG_N2;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) gst(tk->ya, row + j + q * M8, v[q]);
+    half_inverse_row<LOG_N2, true>(v, j, k1, log_n1, hown, TL, T, tk->ya);
     if (!more) break;
     it = nit;
     tk = ntk;
@@ -689,7 +721,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
 }
 
-// Inverse columns + scale + certification.  grid = (N2 / C, tasks).
+// Inverse columns of the half-length inverse + scale + certification.  The
+// rows left y's four-step intermediate in the first N2/2 entries of every row;
+// column n2 < N2/2 gives y_{n2 + (N2/2) n1} = x_{2 m} + i x_{2 m + 1} with
+// 2 m = N2 n1 + 2 n2, and each part is certified as one coefficient.
+// grid = (N2 / 2 / C, tasks).
 template <int LOG_N1>
 __global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n2, int lc, int mode,
                                                  twtab T, double *dbg) {
@@ -715,11 +751,22 @@ __global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n2, 
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const uint32_t n1 = j + q * M8;
-    const uint32_t i = (n1 << log_n2) + n2;
+    const uint32_t i = (n1 << log_n2) + 2 * n2;
     const ci w = ci_scale(ci_conj(v[q]), scale);
-    if (dbg != nullptr && blockIdx.y == 0) dbg_store(dbg, i, w);
-    const unsigned long long cv = certify(w, i, tk.L, mode, acc);
-    if (i < tk.L) gstore(tk.c + i, cv);
+    if (dbg != nullptr && blockIdx.y == 0) {
+      dbg_store(dbg, i, ci{w.rn, w.rh, 0.0, 0.0});
+      dbg_store(dbg, i + 1, ci{w.in, w.ih, 0.0, 0.0});
+    }
+    const unsigned long long c0 = certify_re(w.rn, w.rh, true, i, tk.L, mode, acc);
+    const unsigned long long c1 = certify_re(w.in, w.ih, true, i + 1, tk.L, mode, acc);
+    if (i + 1 < tk.L) {
+      u64x2 pair;
+      pair.x = c0;
+      pair.y = c1;
+      gstore(reinterpret_cast<u64x2 *>(tk.c + i), pair);
+    } else if (i < tk.L) {
+      gstore(tk.c + i, c0);
+    }
   }
   cert_reduce(sh, acc);
   __syncthreads();
@@ -1136,7 +1183,7 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
   {
     const int threads = cfg.cols * static_cast<int>(N1 / 8);
     const size_t lds = sizeof(double2) * lpad_size(N1) * cfg.cols;
-    const dim3 grid(N2 / cfg.cols, ntasks);
+    const dim3 grid(N2 / 2 / cfg.cols, ntasks);
     mark(hk, KIND_COL_INV, 0);
     switch (l1) {
 #define SSA_L(L)                                                                                \

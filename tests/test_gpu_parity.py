@@ -448,7 +448,7 @@ def _valid_shapes(log_n, packed=True):
                 rt = (2 if packed else 1) * rows * (1 << l2) // 8
                 pad1 = (1 << l1) + (1 << l1) // 8
                 pad2 = (1 << l2) + (1 << l2) // 8
-                if (ct > 512 or ct % 64 or pad1 * cols * 16 > 81920 or (1 << l2) % cols
+                if (ct > 512 or ct % 64 or pad1 * cols * 16 > 81920 or (1 << l2) // 2 % cols
                         or rt > 512 or rt % 64 or (2 if packed else 1) * rows * pad2 * 16 > 81920
                         or ((1 << l1) // 2 if packed else (1 << l1)) % rows):
                     continue
