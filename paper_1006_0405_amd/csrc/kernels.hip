@@ -427,6 +427,42 @@ __device__ __forceinline__ ci apply_pass_tw(const ci &v, const twtab &T, uint32_
 // each interleaved pair would cost a full memory round trip.
 __device__ __forceinline__ void stores_after_loads() { __builtin_amdgcn_sched_barrier(0); }
 
+// ---------------------------------------------------------------------------
+// Intermediate arrays between the passes of a product: 20 bytes per element
+// instead of 32.  Element idx of a transform array of N elements is kept as its
+// midpoint (m_re, m_im), a double2 at m[idx], and one radius r at least both
+// half-widths, as the high word of r's binary64 pattern rounded up (for r >= 0
+// the patterns order like the values), a uint32 at r[idx]; the radii follow the
+// N midpoints in the same buffer.  Read back as [m - r, m + r] rounded outward,
+// the element encloses the interval that was stored; the price is the
+// midpoint's rounding and one radius for both parts.
+struct mrbuf {
+  d2v *m;
+  uint32_t *r;
+};
+__device__ __forceinline__ mrbuf mr_of(ci *y, int log_n) {
+  return mrbuf{reinterpret_cast<d2v *>(y), reinterpret_cast<uint32_t *>(y + (size_t(1) << (log_n - 1)))};
+}
+struct mr_raw {
+  d2v m;
+  uint32_t r;
+};
+__device__ __forceinline__ mr_raw mr_load_raw(const mrbuf &b, size_t idx) {
+  return mr_raw{gload(b.m + idx), gload(b.r + idx)};
+}
+__device__ __forceinline__ ci mr_decode(const mr_raw &x) {
+  const double r = __longlong_as_double(static_cast<long long>(static_cast<unsigned long long>(x.r) << 32));
+  return ci{ru_sub(r, x.m.x), ru_add(x.m.x, r), ru_sub(r, x.m.y), ru_add(x.m.y, r)};
+}
+__device__ __forceinline__ ci mr_load(const mrbuf &b, size_t idx) { return mr_decode(mr_load_raw(b, idx)); }
+__device__ __forceinline__ void mr_store(const mrbuf &b, size_t idx, const ci &v) {
+  const double mre = ru_mul(0.5, ru_sub(v.rh, v.rn)), mim = ru_mul(0.5, ru_sub(v.ih, v.in));
+  const double r = dmax(dmax(ru_sub(v.rh, mre), ru_add(v.rn, mre)), dmax(ru_sub(v.ih, mim), ru_add(v.in, mim)));
+  const unsigned long long bits = static_cast<unsigned long long>(__double_as_longlong(r)) + 0xFFFFFFFFull;
+  gstore(b.m + idx, d2v{mre, mim});
+  gstore(b.r + idx, static_cast<uint32_t>(bits >> 32));
+}
+
 // Half-length inverse of a spectrum Z whose inverse transform x is real (the
 // product's coefficients): y_m = x_{2m} + i x_{2m+1}, m < N/2, is the
 // length-N/2 inverse DFT of
@@ -450,7 +486,8 @@ __device__ __forceinline__ ci half_inverse_input(const ci &P, const ci &Q, const
 // exchange buffer (N2/2 elements), TF the table the row DFT reads.
 template <int LOG_N2, bool WAVE, class TT>
 __device__ __forceinline__ void half_inverse_row(const ci v[8], int j, uint32_t k1, int log_n1,
-                                                 double2 *h, const TT &TF, const twtab &T, ci *Y) {
+                                                 double2 *h, const TT &TF, const twtab &T,
+                                                 const mrbuf &Y) {
   constexpr int M8 = 1 << (LOG_N2 - 3);
   const int log_n = log_n1 + LOG_N2;
   ci u[4];
@@ -464,7 +501,16 @@ __device__ __forceinline__ void half_inverse_row(const ci v[8], int j, uint32_t 
   stores_after_loads();
   const size_t row = static_cast<size_t>(k1) << LOG_N2;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) gst(Y, row + j + q * M8, u[q]);
+  for (int q = 0; q < 4; ++q) mr_store(Y, row + j + q * M8, u[q]);
+}
+
+// Column group of a column-pass workgroup, XCD-aware.  Workgroups go round-robin
+// over the 8 XCDs (linear id mod 8; with G a multiple of 8, blockIdx.x mod 8),
+// so block x takes group (x mod 8) (G/8) + x/8: the groups one XCD runs are
+// adjacent in memory, and the cache lines that two neighbouring groups share
+// meet in that XCD's L2 instead of travelling to two of them.
+__device__ __forceinline__ uint32_t xcd_group(uint32_t x, uint32_t G) {
+  return (G & 7u) ? x : (x & 7u) * (G >> 3) + (x >> 3);
 }
 
 // Statistics and carry-scan state of a product are reset by its first pass.
@@ -494,7 +540,7 @@ __global__ __launch_bounds__(512) void k_col_fwd(const task *tasks, int log_n2, 
   const int log_n = LOG_N1 + log_n2;
   constexpr int M8 = 1 << (LOG_N1 - 3);
   const int c = threadIdx.x & ((1 << lc) - 1), j = threadIdx.x >> lc;
-  const uint32_t n2 = (blockIdx.x << lc) + c;
+  const uint32_t n2 = (xcd_group(blockIdx.x, gridDim.x) << lc) + c;
   const bool opb = blockIdx.y != 0;
   if (blockIdx.x == 0 && !opb) reset_product_state(tk);
   uint32_t idx[8], ra[8], rb[8];
@@ -518,12 +564,12 @@ __global__ __launch_bounds__(512) void k_col_fwd(const task *tasks, int log_n2, 
     }
   }
   fft8_group<LOG_N1, false>(v, j, hbuf + c, lc, T);
-  ci *Y = opb ? tk.yb : tk.ya;
+  const mrbuf Y = mr_of(opb ? tk.yb : tk.ya, log_n);
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = apply_pass_tw(v[q], T, n2, j + q * M8, log_n);
   stores_after_loads();
 #pragma unroll
-  for (int q = 0; q < 8; ++q) gst(Y, (static_cast<size_t>(j + q * M8) << log_n2) + n2, v[q]);
+  for (int q = 0; q < 8; ++q) mr_store(Y, (static_cast<size_t>(j + q * M8) << log_n2) + n2, v[q]);
 }
 
 // Rows (one transform per operand): R rows k1 per workgroup, N2/8 threads per
@@ -540,14 +586,14 @@ __device__ __forceinline__ void row_body(const task &tk, int log_n1, int R, cons
   ci va[8], vb[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    va[r] = gld(tk.ya, row + j + r * M8);
-    vb[r] = gld(tk.yb, row + j + r * M8);
+    va[r] = mr_load(mr_of(tk.ya, log_n), row + j + r * M8);
+    vb[r] = mr_load(mr_of(tk.yb, log_n), row + j + r * M8);
   }
   fft8_group<LOG_N2, WAVE>(va, j, hg, 0, T);
   fft8_group<LOG_N2, WAVE>(vb, j, hg, 0, T);
 #pragma unroll
   for (int r = 0; r < 8; ++r) va[r] = ci_conj(ci_mul_fast(va[r], vb[r]));
-  half_inverse_row<LOG_N2, WAVE>(va, j, k1, log_n1, hg, T, T, tk.ya);
+  half_inverse_row<LOG_N2, WAVE>(va, j, k1, log_n1, hg, T, T, mr_of(tk.ya, log_n));
 }
 
 template <int LOG_N2>
@@ -586,7 +632,7 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
   const size_t row = static_cast<size_t>(k1) << LOG_N2;
   ci v[8];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) v[r] = gld(tk.ya, row + j + r * M8);
+  for (int r = 0; r < 8; ++r) v[r] = mr_load(mr_of(tk.ya, log_n), row + j + r * M8);
   fft8_group<LOG_N2, WAVE, true>(v, j, hown, 0, T);
   // partner values, real halves then imaginary halves (workgroup barriers:
   // the partner row may be another wavefront)
@@ -614,7 +660,7 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
     v[r] = ci_conj(separated_product(v[r], W));
   }
   __syncthreads();  // the partner has read this row's buffer
-  half_inverse_row<LOG_N2, WAVE>(v, j, k1, log_n1, hown, T, T, tk.ya);
+  half_inverse_row<LOG_N2, WAVE>(v, j, k1, log_n1, hown, T, T, mr_of(tk.ya, log_n));
 }
 
 template <int LOG_N2>
@@ -669,9 +715,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
   uint32_t k1;
   bool self;
   locate(it, tk, k1, self);
-  ci v[8], nx[8];
+  ci v[8];
+  mr_raw nx[8];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) v[r] = gld(tk->ya, (static_cast<size_t>(k1) << LOG_N2) + j + r * M8);
+  for (int r = 0; r < 8; ++r) v[r] = mr_load(mr_of(tk->ya, log_n), (static_cast<size_t>(k1) << LOG_N2) + j + r * M8);
   for (;;) {
     const uint32_t nit = it + gridDim.x;
     const bool more = nit < total;
@@ -681,7 +728,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     if (more) {
       locate(nit, ntk, nk1, nself);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) nx[r] = gld(ntk->ya, (static_cast<size_t>(nk1) << LOG_N2) + j + r * M8);
+      for (int r = 0; r < 8; ++r)
+        nx[r] = mr_load_raw(mr_of(ntk->ya, log_n), (static_cast<size_t>(nk1) << LOG_N2) + j + r * M8);
     }
     double2 *hown = hbuf + static_cast<size_t>(rg) * rowslots;
     double2 *hpart = self ? hown : hbuf + static_cast<size_t>(rg ^ 1) * rowslots;
@@ -710,14 +758,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
       v[r] = ci_conj(separated_product(v[r], W));
     }
     __syncthreads();  // the partner has read this row's buffer
-    half_inverse_row<LOG_N2, true>(v, j, k1, log_n1, hown, TL, T, tk->ya);
+    half_inverse_row<LOG_N2, true>(v, j, k1, log_n1, hown, TL, T, mr_of(tk->ya, log_n));
     if (!more) break;
     it = nit;
     tk = ntk;
     k1 = nk1;
     self = nself;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = nx[r];
+    for (int r = 0; r < 8; ++r) v[r] = mr_decode(nx[r]);
   }
 }
 
@@ -737,13 +785,13 @@ __global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n2, 
   const int log_n = LOG_N1 + log_n2;
   constexpr int M8 = 1 << (LOG_N1 - 3);
   const int c = threadIdx.x & ((1 << lc) - 1), j = threadIdx.x >> lc;
-  const uint32_t n2 = (blockIdx.x << lc) + c;
+  const uint32_t n2 = (xcd_group(blockIdx.x, gridDim.x) << lc) + c;
   if (threadIdx.x == 0) sh = cert_shared{0ull, 0ull, 0u, 0u};
   ci v[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const uint32_t k1 = j + r * M8;
-    v[r] = ci_conj(gld(tk.ya, (static_cast<size_t>(k1) << log_n2) + n2));
+    v[r] = ci_conj(mr_load(mr_of(tk.ya, log_n), (static_cast<size_t>(k1) << log_n2) + n2));
   }
   fft8_group<LOG_N1, false>(v, j, hbuf + c, lc, T);
   const double scale = ldexp(1.0, -log_n);
