@@ -32,7 +32,8 @@ METRIC = "certified products/s & HBM GB/s: FP64 interval vs FP32+fallback, 2^18 
 UNIT = "certified products/s"
 NBYTES = 75_000
 HBM_PEAK_GBPS = 8000.0
-ELEM = 32  # bytes of one FP64 rectangular complex interval
+ELEM = 32  # bytes of one FP64 rectangular complex interval (the standalone FFT's element)
+MRELEM = 20  # bytes of one element of the arrays between the product's passes
 
 
 def kernel_source_hash():
@@ -43,16 +44,17 @@ def kernel_source_hash():
 
 
 def alg_bytes_per_product(kind, N, L, nbytes_total, packed=True):
-    """Algorithmic HBM bytes one product needs in each kernel: every FP64
-    interval array element read or written once is 32 bytes.  Packed: one
-    transformed array (a + i b); separate: one array per operand.
-    The inverse is the half-length one of the real coefficients: N/2 elements
-    go from the row pass to the inverse column pass."""
+    """Algorithmic HBM bytes one product needs in each kernel: every element of
+    an array between two passes, read or written once, is 20 bytes (FP64
+    midpoint pair and a 32-bit radius).  Packed: one transformed array
+    (a + i b); separate: one array per operand.  The inverse is the half-length
+    one of the real coefficients: N/2 elements go from the row pass to the
+    inverse column pass."""
     arrays = 1 if packed else 2
     return {
-        "col_fwd": arrays * N * ELEM + nbytes_total,   # read digits, write the column-transformed array(s)
-        "row": arrays * N * ELEM + N // 2 * ELEM,      # read the array(s), write the half-length inverse's rows
-        "col_inv": N // 2 * ELEM + 8 * L,              # read those, write the certified int64 coefficients
+        "col_fwd": arrays * N * MRELEM + nbytes_total,     # read digits, write the column-transformed array(s)
+        "row": arrays * N * MRELEM + N // 2 * MRELEM,      # read the array(s), write the half-length inverse's rows
+        "col_inv": N // 2 * MRELEM + 8 * L,                # read those, write the certified int64 coefficients
         "carry": 8 * L + nbytes_total,                 # read coefficients, write the product bytes
     }[kind]
 

@@ -853,7 +853,7 @@ __global__ __launch_bounds__(512) void k_fft_col(const double *x, double *y, int
   const int log_n = LOG_N1 + log_n2;
   constexpr int M8 = 1 << (LOG_N1 - 3);
   const int c = threadIdx.x & ((1 << lc) - 1), j = threadIdx.x >> lc;
-  const uint32_t n2 = (blockIdx.x << lc) + c;
+  const uint32_t n2 = (xcd_group(blockIdx.x, gridDim.x) << lc) + c;
   const size_t base = static_cast<size_t>(blockIdx.y) << log_n;
   ci v[8];
 #pragma unroll
