@@ -457,7 +457,7 @@ def main():
             "fft_length": N,
             "digit_bits": 8,
             "transform": "one complex FFT of a + i b" if packed else "one FFT per operand",
-            "launch_shape": {k: tuned[k] for k in ("log_n1", "cols", "rows", "persistent")},
+            "launch_shape": {k: tuned[k] for k in ("log_n1", "cols", "rows", "persistent", "inv_cols")},
         },
         "roofline": {
             "bound": "hbm",

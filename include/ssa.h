@@ -191,9 +191,10 @@ ssa_status ssa_fft_forward(ssa_plan *plan, int log_n, size_t count, const double
 
 /* Launch shape of the three-pass path (transforms longer than 2^12) for one
  * transform length 2^log_n: column transforms of length 2^log_n1 (rows of
- * 2^(log_n - log_n1)), `cols` adjacent columns per column-pass workgroup,
- * `rows` rows (row pairs for the packed transform) per row-pass workgroup, and
- * whether the row pass runs persistent. */
+ * 2^(log_n - log_n1)), `cols` adjacent columns per forward column-pass
+ * workgroup, `rows` rows (row pairs for the packed transform) per row-pass
+ * workgroup, whether the row pass runs persistent, and `inv_cols` adjacent
+ * columns per inverse column-pass workgroup. */
 typedef struct {
   int log_n1;
   int cols;
@@ -201,6 +202,8 @@ typedef struct {
   int persistent;  /* 1: the row pass runs as a persistent kernel (as many workgroups as
                       are resident) that prefetches its next rows while computing the
                       current ones; packed plans with rows of at most 2^9 points only */
+  int inv_cols;    /* set_config: 0 means the same as cols; get_config and the
+                      autotuner return the value in use */
 } ssa_launch_config;
 
 ssa_status ssa_plan_get_config(const ssa_plan *plan, int log_n, ssa_launch_config *cfg_host);

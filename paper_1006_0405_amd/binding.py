@@ -52,11 +52,11 @@ class PlanOpts(ctypes.Structure):
 
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("log_n1", ctypes.c_int), ("cols", ctypes.c_int), ("rows", ctypes.c_int),
-                ("persistent", ctypes.c_int)]
+                ("persistent", ctypes.c_int), ("inv_cols", ctypes.c_int)]
 
     def as_dict(self):
         return {"log_n1": self.log_n1, "cols": self.cols, "rows": self.rows,
-                "persistent": self.persistent}
+                "persistent": self.persistent, "inv_cols": self.inv_cols}
 
 
 class Stats(ctypes.Structure):
@@ -239,8 +239,9 @@ class Plan:
         _check(lib().ssa_plan_get_config(self.handle, log_n, ctypes.byref(c)), "ssa_plan_get_config")
         return c.as_dict()
 
-    def set_config(self, log_n, log_n1, cols, rows, persistent=0):
-        c = LaunchConfig(log_n1, cols, rows, int(persistent))
+    def set_config(self, log_n, log_n1, cols, rows, persistent=0, inv_cols=0):
+        """inv_cols: columns per inverse column-pass workgroup (0: as cols)."""
+        c = LaunchConfig(log_n1, cols, rows, int(persistent), int(inv_cols))
         _check(lib().ssa_plan_set_config(self.handle, log_n, ctypes.byref(c)), "ssa_plan_set_config")
 
     def autotune(self, log_n, count=16, cache=None):
@@ -260,7 +261,8 @@ class Plan:
                 table = {}
             if key in table:
                 c = table[key]
-                self.set_config(log_n, c["log_n1"], c["cols"], c["rows"], c.get("persistent", 0))
+                self.set_config(log_n, c["log_n1"], c["cols"], c["rows"], c.get("persistent", 0),
+                                c.get("inv_cols", 0))
                 return dict(c, cached=True)
         best = LaunchConfig()
         ms = ctypes.c_double(0)

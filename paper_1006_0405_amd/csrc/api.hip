@@ -43,6 +43,7 @@ launch_cfg default_cfg(int log_n, int pack) {
   c.cols = std::max(2, std::min(32, 2048 / N1));
   c.pack = pack;
   c.persist = 0;
+  c.icols = c.cols;
   const int t = N2 / 8;  // threads per row
   if (pack)
     c.rows = std::max(1, std::min(N1 / 2, 128 / t));
@@ -59,10 +60,12 @@ bool cfg_valid(const launch_cfg &c, int log_n) {
   if (c.log_n2 != log_n - c.log_n1) return false;
   const int N1 = 1 << c.log_n1, N2 = 1 << c.log_n2;
   const auto pow2 = [](int x) { return x > 0 && (x & (x - 1)) == 0; };
-  if (!pow2(c.cols) || (N2 / 2) % c.cols) return false;  // inverse columns: N2/2 of them
-  const int ct = c.cols * N1 / 8;
-  if (ct > 512 || ct % 64) return false;
-  if ((N1 + N1 / 8) * static_cast<size_t>(c.cols) * 16 > 81920) return false;
+  const auto cols_ok = [&](int cols, int ncols) {
+    const int ct = cols * N1 / 8;
+    return pow2(cols) && ncols % cols == 0 && ct <= 512 && ct % 64 == 0 &&
+           (N1 + N1 / 8) * static_cast<size_t>(cols) * 16 <= 81920;
+  };
+  if (!cols_ok(c.cols, N2) || !cols_ok(c.icols, N2 / 2)) return false;  // inverse: N2/2 columns
   const int per = c.pack ? 2 : 1;
   if (!pow2(c.rows) || (c.pack ? (N1 / 2) % c.rows : N1 % c.rows)) return false;
   const int rt = per * c.rows * N2 / 8;
@@ -761,13 +764,14 @@ static launch_cfg from_public(const ssa_launch_config &c, int log_n, int pack) {
   r.rows = c.rows;
   r.pack = pack;
   r.persist = c.persistent;
+  r.icols = c.inv_cols ? c.inv_cols : c.cols;
   return r;
 }
 
 ssa_status ssa_plan_get_config(const ssa_plan *plan, int log_n, ssa_launch_config *cfg) {
   if (!plan || !cfg || log_n <= SMALL_MAX_LOG || log_n > MAX_LOG_N) return SSA_INVALID_ARGUMENT;
   const launch_cfg &c = plan->cfg[log_n];
-  *cfg = ssa_launch_config{c.log_n1, c.cols, c.rows, c.persist};
+  *cfg = ssa_launch_config{c.log_n1, c.cols, c.rows, c.persist, c.icols};
   return SSA_OK;
 }
 
@@ -838,27 +842,38 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
   double bestms = 1e30;
   int tried = 0;
   bool ok = true;
+  const auto time_shape = [&](const launch_cfg &c) {
+    plan->cfg[log_n] = c;
+    ok = hip_ok(enqueue_batch(bt, s, nullptr));  // warm-up
+    if (!ok) return;
+    const int reps = 3;
+    ok = hip_ok(hipEventRecord(e0, s));
+    for (int k = 0; k < reps && ok; ++k) ok = hip_ok(enqueue_batch(bt, s, nullptr));
+    ok = ok && hip_ok(hipEventRecord(e1, s)) && hip_ok(hipEventSynchronize(e1));
+    float ms = 0.f;
+    ok = ok && hip_ok(hipEventElapsedTime(&ms, e0, e1));
+    ++tried;
+    if (ok && ms / reps < bestms) {
+      bestms = ms / reps;
+      bestc = c;
+    }
+  };
+  // every shape with one column count for both column passes, then the inverse
+  // column pass's own count for the best of them (the passes are separate
+  // kernels, so the second search is independent of the first's other choices)
   for (int l1 = 6; l1 <= 11 && ok; ++l1)
     for (int cols = 1; cols <= 32 && ok; cols *= 2)
       for (int rows = 1; rows <= 64 && ok; rows *= 2)
         for (int persist = 0; persist <= 1 && ok; ++persist) {
-        launch_cfg c{l1, log_n - l1, cols, rows, pack, persist};
-        if (!cfg_valid(c, log_n)) continue;
-        plan->cfg[log_n] = c;
-        ok = hip_ok(enqueue_batch(bt, s, nullptr));  // warm-up
-        if (!ok) break;
-        const int reps = 3;
-        ok = hip_ok(hipEventRecord(e0, s));
-        for (int k = 0; k < reps && ok; ++k) ok = hip_ok(enqueue_batch(bt, s, nullptr));
-        ok = ok && hip_ok(hipEventRecord(e1, s)) && hip_ok(hipEventSynchronize(e1));
-        float ms = 0.f;
-        ok = ok && hip_ok(hipEventElapsedTime(&ms, e0, e1));
-        ++tried;
-        if (ok && ms / reps < bestms) {
-          bestms = ms / reps;
-          bestc = c;
+          const launch_cfg c{l1, log_n - l1, cols, rows, pack, persist, cols};
+          if (cfg_valid(c, log_n)) time_shape(c);
         }
-      }
+  const launch_cfg first = bestc;
+  for (int icols = 1; icols <= 32 && ok; icols *= 2) {
+    launch_cfg c = first;
+    c.icols = icols;
+    if (icols != first.icols && cfg_valid(c, log_n)) time_shape(c);
+  }
   plan->cfg[log_n] = ok ? bestc : keep;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -869,7 +884,7 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
     hipGetLastError();
     return SSA_DEVICE_ERROR;
   }
-  *best = ssa_launch_config{bestc.log_n1, bestc.cols, bestc.rows, bestc.persist};
+  *best = ssa_launch_config{bestc.log_n1, bestc.cols, bestc.rows, bestc.persist, bestc.icols};
   *best_ms_host = bestms;
   if (tried_host) *tried_host = tried;
   return SSA_OK;

@@ -62,6 +62,7 @@ struct launch_cfg {
   int rows;    // rows (row pairs when packed) per workgroup in the row pass
   int pack;    // 1: one complex transform of a + i b; 0: one transform per operand
   int persist; // 1: persistent row-pair pass with next-item prefetch (pack, rows <= 2^9)
+  int icols;   // columns per workgroup in the inverse column pass
 };
 
 struct twtab_host {

@@ -1229,14 +1229,16 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
     if (e != hipSuccess) return e;
   }
   {
-    const int threads = cfg.cols * static_cast<int>(N1 / 8);
-    const size_t lds = sizeof(double2) * lpad_size(N1) * cfg.cols;
-    const dim3 grid(N2 / 2 / cfg.cols, ntasks);
+    const int lci = log2_int(cfg.icols);
+    if ((1 << lci) != cfg.icols) return hipErrorInvalidValue;
+    const int threads = cfg.icols * static_cast<int>(N1 / 8);
+    const size_t lds = sizeof(double2) * lpad_size(N1) * cfg.icols;
+    const dim3 grid(N2 / 2 / cfg.icols, ntasks);
     mark(hk, KIND_COL_INV, 0);
     switch (l1) {
 #define SSA_L(L)                                                                                \
   case L:                                                                                       \
-    hipLaunchKernelGGL(k_col_inv<L>, grid, dim3(threads), lds, s, d_tasks, l2, lc, cert_mode,  \
+    hipLaunchKernelGGL(k_col_inv<L>, grid, dim3(threads), lds, s, d_tasks, l2, lci, cert_mode, \
                        T, dbg);                                                                 \
     break;
       SSA_PASS_LENGTHS(SSA_L)

@@ -472,7 +472,7 @@ def test_every_launch_shape_gives_the_same_product(nbytes, separate):
     for l1, cols, rows, pers in shapes:
         plan.set_config(log_n, l1, cols, rows, pers)
         assert plan.get_config(log_n) == {"log_n1": l1, "cols": cols, "rows": rows,
-                                          "persistent": pers}
+                                          "persistent": pers, "inv_cols": cols}
         st, out = plan.mul(a, b)
         assert st == binding.SSA_OK, (l1, cols, rows, pers)
         assert np.array_equal(_np(out), want), (l1, cols, rows, pers)
@@ -482,6 +482,38 @@ def test_every_launch_shape_gives_the_same_product(nbytes, separate):
         plan.set_config(log_n, log_n // 2, 3, 1)
     with pytest.raises(binding.SsaError):
         plan.set_config(log_n, 6, 8, 1, 2)  # persistent flag out of range
+    with pytest.raises(binding.SsaError):
+        plan.set_config(log_n, shapes[0][0], shapes[0][1], shapes[0][2], 0, 3)  # inv_cols not 2^k
+    plan.close()
+
+
+@pytest.mark.parametrize("nbytes", [5000, 30000, 75000])
+def test_inverse_column_count_gives_the_same_product(nbytes):
+    """The inverse column pass with its own column count (every valid one), the
+    other passes fixed: random and all-0xFF operands, all exact."""
+    plan = binding.Plan(nbytes, nbytes)
+    log_n = binding.fft_size(nbytes, nbytes).bit_length() - 1
+    l1 = log_n // 2
+    N1, N2 = 1 << l1, 1 << (log_n - l1)
+    a, b = pair(nbytes + 5, nbytes, nbytes - 3)
+    f = all_ff(nbytes)
+    want_ab, want_ff = int_product(a, b), int_product(f, f)
+    cols = 4 if N1 <= 1024 else 2
+    rows = max(1, 32 // (N2 // 8))  # row-pair workgroups of whole wavefronts
+    tried = 0
+    for ic in (1, 2, 4, 8, 16, 32):
+        if ic * N1 // 8 > 512 or ic * N1 // 8 % 64 or (N1 + N1 // 8) * ic * 16 > 81920 or (N2 // 2) % ic:
+            with pytest.raises(binding.SsaError):
+                plan.set_config(log_n, l1, cols, rows, 0, ic)
+            continue
+        plan.set_config(log_n, l1, cols, rows, 0, ic)
+        assert plan.get_config(log_n)["inv_cols"] == ic
+        for x, y, want in ((a, b, want_ab), (f, f, want_ff)):
+            st, out = plan.mul(x, y)
+            assert st == binding.SSA_OK, ic
+            assert np.array_equal(_np(out), want), ic
+        tried += 1
+    assert tried >= 2
     plan.close()
 
 
@@ -522,7 +554,8 @@ def test_autotuner_choice_is_used_and_correct(tmp_path):
     print("autotune 2^18:", res)
     again = plan.autotune(18, count=8, cache=cache)
     assert again["cached"] and again["log_n1"] == res["log_n1"]
-    assert plan.get_config(18) == {k: res[k] for k in ("log_n1", "cols", "rows", "persistent")}
+    assert plan.get_config(18) == {k: res[k] for k in ("log_n1", "cols", "rows", "persistent",
+                                                       "inv_cols")}
     a, b = pair(2, n)
     st, out = plan.mul(a, b)
     assert st == binding.SSA_OK and np.array_equal(_np(out), int_product(a, b))
