@@ -334,6 +334,9 @@ def main():
                     help="one forward FFT per operand (the fast convolution box literally) "
                          "instead of one FFT of a + i b")
     ap.add_argument("--cpu-workers", type=int, default=0, help="0 = min(16, host cores)")
+    ap.add_argument("--shape", default="",
+                    help="launch shape 'log_n1,cols,rows,persistent,inv_cols' for the main "
+                         "workload instead of the autotuner's choice (profiling runs pin it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (torch), the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings")
@@ -374,7 +377,12 @@ def main():
     plan = binding.Plan(NBYTES, NBYTES, separate_transforms=not packed)
     N = binding.fft_size(NBYTES, NBYTES)
     log_n = N.bit_length() - 1
-    tuned = plan.autotune(log_n, count=B)  # launch shape for this length, timed on the device
+    if args.shape:
+        sh = [int(v) for v in args.shape.split(",")]
+        plan.set_config(log_n, *sh)
+        tuned = plan.get_config(log_n)
+    else:
+        tuned = plan.autotune(log_n, count=B)  # launch shape for this length, timed on the device
     batch = binding.Batch(plan, A, Bs)
 
     # correctness of the timed work, checked once outside the timed region
