@@ -210,11 +210,13 @@ ssa_status ssa_plan_get_config(const ssa_plan *plan, int log_n, ssa_launch_confi
 /* Rejects (SSA_INVALID_ARGUMENT) shapes that do not fit the kernels: workgroups
  * over 512 threads or not whole wavefronts, LDS over 64 KiB, uneven grids. */
 ssa_status ssa_plan_set_config(ssa_plan *plan, int log_n, const ssa_launch_config *cfg_host);
-/* Times every valid shape for transforms of length 2^log_n (12 < log_n <= the
- * plan's largest) on `count` synthetic products of that length (device memory
- * allocated for the call and released), keeps the fastest in the plan and
- * returns it with its time per batch of `count` products (milliseconds) and the
- * number of shapes tried.  Synchronises the plan's stream. */
+/* Times every valid shape with inv_cols == cols for transforms of length
+ * 2^log_n (12 < log_n <= the plan's largest) on `count` synthetic products of
+ * that length (device memory allocated for the call and released), then, from
+ * the fastest, every other inv_cols and after that every other cols; keeps the
+ * fastest in the plan and returns it with its time per batch of `count`
+ * products (milliseconds) and the number of shapes tried.  Synchronises the
+ * plan's stream. */
 ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_config *best_host,
                              double *best_ms_host, int *tried_host);
 

@@ -858,9 +858,10 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
       bestc = c;
     }
   };
-  // every shape with one column count for both column passes, then the inverse
-  // column pass's own count for the best of them (the passes are separate
-  // kernels, so the second search is independent of the first's other choices)
+  // every shape with one column count for both column passes; then, the rest of
+  // the best shape kept, the inverse column pass's own count, and after it the
+  // forward column pass's count (the two column passes are separate kernels, so
+  // each search only moves its own pass's time)
   for (int l1 = 6; l1 <= 11 && ok; ++l1)
     for (int cols = 1; cols <= 32 && ok; cols *= 2)
       for (int rows = 1; rows <= 64 && ok; rows *= 2)
@@ -868,11 +869,13 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
           const launch_cfg c{l1, log_n - l1, cols, rows, pack, persist, cols};
           if (cfg_valid(c, log_n)) time_shape(c);
         }
-  const launch_cfg first = bestc;
-  for (int icols = 1; icols <= 32 && ok; icols *= 2) {
-    launch_cfg c = first;
-    c.icols = icols;
-    if (icols != first.icols && cfg_valid(c, log_n)) time_shape(c);
+  for (int pass = 0; pass < 2 && ok; ++pass) {
+    const launch_cfg base = bestc;
+    for (int k = 1; k <= 32 && ok; k *= 2) {
+      launch_cfg c = base;
+      (pass == 0 ? c.icols : c.cols) = k;
+      if (k != (pass == 0 ? base.icols : base.cols) && cfg_valid(c, log_n)) time_shape(c);
+    }
   }
   plan->cfg[log_n] = ok ? bestc : keep;
   hipEventDestroy(e0);
