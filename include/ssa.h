@@ -48,6 +48,7 @@ typedef enum {
 } ssa_status;
 
 enum { SSA_FP64 = 0, SSA_FP32_FALLBACK = 1 };
+enum { SSA_ARITH_RECT = 0, SSA_ARITH_DISC = 1 };
 enum { SSA_CERTIFY_ONE_INTEGER = 0, SSA_CERTIFY_HALF_INTEGER = 1 };
 
 typedef struct {
@@ -74,6 +75,15 @@ typedef struct {
                               2^22 points; the plan allocates for it.  The product is
                               the same; stats.refined says which run produced it.
                               Batches report the base-256 outcome.                 */
+  int arithmetic;          /* SSA_ARITH_RECT (default): rectangular complex intervals
+                              (section 2.5) everywhere.  SSA_ARITH_DISC: products of
+                              transform length above 2^12 run the three passes in
+                              FP64 midpoint-radius discs (circular containment sets,
+                              section 4), which a rotation by a root of unity does not
+                              enlarge; needs the packed transform (separate_transforms
+                              = 0; SSA_INVALID_ARGUMENT otherwise) and a launch shape
+                              without the persistent row pass.  Shorter products stay
+                              rectangular.  Same products.                        */
 } ssa_plan_opts;
 
 typedef struct {

@@ -27,6 +27,8 @@ STATUS_NAMES = {0: "OK", 1: "ENCLOSURE_TOO_WIDE", 2: "INVALID_ARGUMENT", 3: "OUT
 SSA_FP64 = 0
 SSA_FP32_FALLBACK = 1
 PRECISIONS = {"fp64": SSA_FP64, "fp32_fallback": SSA_FP32_FALLBACK}
+SSA_ARITH_RECT, SSA_ARITH_DISC = 0, 1
+ARITHMETICS = {"rect": SSA_ARITH_RECT, "disc": SSA_ARITH_DISC}
 SSA_CERTIFY_ONE_INTEGER = 0
 SSA_CERTIFY_HALF_INTEGER = 1
 
@@ -47,7 +49,7 @@ class SsaError(RuntimeError):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("digit_bits", ctypes.c_int),
                 ("certify_mode", ctypes.c_int), ("separate_transforms", ctypes.c_int),
-                ("refine_digits", ctypes.c_int)]
+                ("refine_digits", ctypes.c_int), ("arithmetic", ctypes.c_int)]
 
 
 class LaunchConfig(ctypes.Structure):
@@ -165,7 +167,7 @@ class Plan:
 
     def __init__(self, max_na, max_nb, digit_bits=8, certify_mode=SSA_CERTIFY_ONE_INTEGER,
                  separate_transforms=False, precision="fp64", stream=None, device=None,
-                 refine_digits=False):
+                 refine_digits=False, arithmetic="rect"):
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.digit_bits = digit_bits
@@ -173,8 +175,12 @@ class Plan:
         if precision not in PRECISIONS:
             raise SsaError("precision %r is not available (one of %s)" % (precision, sorted(PRECISIONS)))
         self.precision = precision
+        if arithmetic not in ARITHMETICS:
+            raise SsaError("arithmetic %r is not available (one of %s)" % (arithmetic, sorted(ARITHMETICS)))
+        self.arithmetic = arithmetic
         opts = PlanOpts(PRECISIONS[precision], digit_bits, certify_mode,
-                        int(bool(separate_transforms)), int(bool(refine_digits)))
+                        int(bool(separate_transforms)), int(bool(refine_digits)),
+                        ARITHMETICS[arithmetic])
         h = _vp()
         with torch.cuda.device(self.device):
             _check(lib().ssa_plan_create(ctypes.byref(h), max_na, max_nb, ctypes.byref(opts),
@@ -252,9 +258,9 @@ class Plan:
         if cache:
             import json
             props = torch.cuda.get_device_properties(self.device)
-            key = "%s/log_n=%d/digit_bits=%d/separate=%d" % (
+            key = "%s/log_n=%d/digit_bits=%d/separate=%d/arithmetic=%s" % (
                 getattr(props, "gcnArchName", props.name), log_n, self.digit_bits,
-                int(self.separate_transforms))
+                int(self.separate_transforms), self.arithmetic)
             try:
                 table = json.load(open(cache))
             except (OSError, ValueError):

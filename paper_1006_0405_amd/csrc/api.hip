@@ -35,7 +35,7 @@ uint64_t digits(size_t n, int bits) { return bits == 4 ? 2 * uint64_t(n) : uint6
 // Default launch shape of the three-pass path for N = 2^log_n (8 elements per
 // thread): C adjacent columns per column-pass workgroup (256 threads, 512 for
 // N1 = 2^11), and G rows (or row pairs) per row-pass workgroup.
-launch_cfg default_cfg(int log_n, int pack) {
+launch_cfg default_cfg(int log_n, int pack, int disc) {
   launch_cfg c;
   c.log_n1 = log_n / 2;
   c.log_n2 = log_n - c.log_n1;
@@ -44,6 +44,7 @@ launch_cfg default_cfg(int log_n, int pack) {
   c.pack = pack;
   c.persist = 0;
   c.icols = c.cols;
+  c.disc = disc;
   const int t = N2 / 8;  // threads per row
   if (pack)
     c.rows = std::max(1, std::min(N1 / 2, 128 / t));
@@ -72,6 +73,7 @@ bool cfg_valid(const launch_cfg &c, int log_n) {
   if (rt > 512 || rt % 64) return false;
   if (static_cast<size_t>(per) * c.rows * (N2 + N2 / 8) * 16 > 81920) return false;
   if (c.persist != 0 && c.persist != 1) return false;
+  if (c.disc && (!c.pack || c.persist)) return false;  // discs: packed transform, plain row pass
   // the persistent row pass: packed rows of one wavefront, twiddle levels in LDS
   if (c.persist && (!c.pack || c.log_n2 > 9 ||
                     (2 * static_cast<size_t>(c.rows) * (N2 + N2 / 8) + (size_t(2) << c.log_n2)) * 16 > 81920))
@@ -299,7 +301,9 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
       (o.certify_mode != SSA_CERTIFY_ONE_INTEGER && o.certify_mode != SSA_CERTIFY_HALF_INTEGER) ||
       (o.precision != SSA_FP64 && o.precision != SSA_FP32_FALLBACK) ||
       (o.separate_transforms != 0 && o.separate_transforms != 1) ||
-      (o.refine_digits != 0 && (o.refine_digits != 1 || o.digit_bits != 8)))
+      (o.refine_digits != 0 && (o.refine_digits != 1 || o.digit_bits != 8)) ||
+      (o.arithmetic != SSA_ARITH_RECT && o.arithmetic != SSA_ARITH_DISC) ||
+      (o.arithmetic == SSA_ARITH_DISC && o.separate_transforms != 0))
     return SSA_INVALID_ARGUMENT;
   const uint64_t L = digits(max_na, o.digit_bits) + digits(max_nb, o.digit_bits) - 1;
   const int log_nmax = log_n_for(L);
@@ -324,7 +328,7 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
   p->log_nref = log_nref;
   p->log_ntab = log_nalloc;
   for (int l = SMALL_MAX_LOG + 1; l <= MAX_LOG_N; ++l)
-    p->cfg[l] = default_cfg(l, o.separate_transforms ? 0 : 1);
+    p->cfg[l] = default_cfg(l, o.separate_transforms ? 0 : 1, o.arithmetic == SSA_ARITH_DISC ? 1 : 0);
   const size_t N = size_t(1) << log_nalloc;
   const size_t ntiles = (max_na + max_nb + CARRY_TILE - 1) / CARRY_TILE;
   bool ok = hip_ok(hipMalloc(&p->tab, sizeof(double2) << (p->log_ntab + 1))) &&  // level tables
@@ -756,7 +760,7 @@ ssa_status ssa_mul_batch(ssa_plan *plan, size_t count, const uint8_t *const *a, 
 // ---------------------------------------------------------------------------
 // Launch shapes and the autotuner
 
-static launch_cfg from_public(const ssa_launch_config &c, int log_n, int pack) {
+static launch_cfg from_public(const ssa_launch_config &c, int log_n, int pack, int disc) {
   launch_cfg r;
   r.log_n1 = c.log_n1;
   r.log_n2 = log_n - c.log_n1;
@@ -765,6 +769,7 @@ static launch_cfg from_public(const ssa_launch_config &c, int log_n, int pack) {
   r.pack = pack;
   r.persist = c.persistent;
   r.icols = c.inv_cols ? c.inv_cols : c.cols;
+  r.disc = disc;
   return r;
 }
 
@@ -777,7 +782,8 @@ ssa_status ssa_plan_get_config(const ssa_plan *plan, int log_n, ssa_launch_confi
 
 ssa_status ssa_plan_set_config(ssa_plan *plan, int log_n, const ssa_launch_config *cfg) {
   if (!plan || !cfg || log_n <= SMALL_MAX_LOG || log_n > MAX_LOG_N) return SSA_INVALID_ARGUMENT;
-  const launch_cfg c = from_public(*cfg, log_n, plan->opts.separate_transforms ? 0 : 1);
+  const launch_cfg c = from_public(*cfg, log_n, plan->opts.separate_transforms ? 0 : 1,
+                                   plan->opts.arithmetic == SSA_ARITH_DISC ? 1 : 0);
   if (!cfg_valid(c, log_n)) return SSA_INVALID_ARGUMENT;
   plan->cfg[log_n] = c;
   return SSA_OK;
@@ -790,6 +796,7 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
     return SSA_INVALID_ARGUMENT;
   const int bits = plan->opts.digit_bits;
   const int pack = plan->opts.separate_transforms ? 0 : 1;
+  const int disc = plan->opts.arithmetic == SSA_ARITH_DISC ? 1 : 0;
   // equal operands as long as the plan allows, at most 2^(log_n - 1) digits each;
   // their transform length must be exactly 2^log_n
   const size_t nbytes = std::min(std::min(plan->max_na, plan->max_nb),
@@ -866,7 +873,7 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
     for (int cols = 1; cols <= 32 && ok; cols *= 2)
       for (int rows = 1; rows <= 64 && ok; rows *= 2)
         for (int persist = 0; persist <= 1 && ok; ++persist) {
-          const launch_cfg c{l1, log_n - l1, cols, rows, pack, persist, cols};
+          const launch_cfg c{l1, log_n - l1, cols, rows, pack, persist, cols, disc};
           if (cfg_valid(c, log_n)) time_shape(c);
         }
   for (int pass = 0; pass < 2 && ok; ++pass) {

@@ -2,7 +2,7 @@
 // length-4 DFT (inner twiddles +-1, +-i are exact permutations in rectangular
 // interval arithmetic, so they cause no wrapping) and the twiddle table.
 #pragma once
-#include "ia.hpp"
+#include "disc64.hpp"
 
 namespace ssa {
 
@@ -44,14 +44,14 @@ template <class T> __device__ __forceinline__ void gstore(T *p, T v) {
 
 // Length-4 DFT with omega_4 = +i:  y0 = a + c, y2 = a - c, y1 = b + i d,
 // y3 = b - i d, where a = v0 + v2, b = v0 - v2, c = v1 + v3, d = v1 - v3.
-__device__ __forceinline__ void radix4(ci v[4]) {
-  const ci a = ci_add(v[0], v[2]), b = ci_sub(v[0], v[2]);
-  const ci c = ci_add(v[1], v[3]), d = ci_sub(v[1], v[3]);
-  const ci id = ci_mul_i(d);
-  v[0] = ci_add(a, c);
-  v[2] = ci_sub(a, c);
-  v[1] = ci_add(b, id);
-  v[3] = ci_sub(b, id);
+template <class E> __device__ __forceinline__ void radix4(E v[4]) {
+  const E a = e_add(v[0], v[2]), b = e_sub(v[0], v[2]);
+  const E c = e_add(v[1], v[3]), d = e_sub(v[1], v[3]);
+  const E id = e_mul_i(d);
+  v[0] = e_add(a, c);
+  v[2] = e_sub(a, c);
+  v[1] = e_add(b, id);
+  v[3] = e_sub(b, id);
 }
 
 // Twiddle tables by level: tab[2^l + u] = omega_{2^l}^u (l <= log_ntab,

@@ -56,16 +56,22 @@ __device__ __forceinline__ ci ci_mul_w83(const ci &z, double c, double e) {
 // a_r = v_r + v_{r+4}, b_r = (v_r - v_{r+4}) omega_8^r (r < 4);
 // y_{2m} = DFT4(a)_m, y_{2m+1} = DFT4(b)_m.  Only omega_8 and omega_8^3 are
 // interval-inexact; omega_8^2 = i is a permutation.
-__device__ __forceinline__ void radix8(ci v[8], double c8, double e8) {
-  ci a[4], b[4];
+// For discs omega_8 and omega_8^3 are rotations by the point (+-c8, c8).
+__device__ __forceinline__ ci e_mul_w8(const ci &z, double c8, double e8) { return ci_mul_w8(z, c8, e8); }
+__device__ __forceinline__ ci e_mul_w83(const ci &z, double c8, double e8) { return ci_mul_w83(z, c8, e8); }
+__device__ __forceinline__ md e_mul_w8(const md &z, double c8, double e8) { return md_tw(z, c8, c8, e8); }
+__device__ __forceinline__ md e_mul_w83(const md &z, double c8, double e8) { return md_tw(z, -c8, c8, e8); }
+
+template <class E> __device__ __forceinline__ void radix8(E v[8], double c8, double e8) {
+  E a[4], b[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    a[r] = ci_add(v[r], v[r + 4]);
-    b[r] = ci_sub(v[r], v[r + 4]);
+    a[r] = e_add(v[r], v[r + 4]);
+    b[r] = e_sub(v[r], v[r + 4]);
   }
-  b[1] = ci_mul_w8(b[1], c8, e8);
-  b[2] = ci_mul_i(b[2]);
-  b[3] = ci_mul_w83(b[3], c8, e8);
+  b[1] = e_mul_w8(b[1], c8, e8);
+  b[2] = e_mul_i(b[2]);
+  b[3] = e_mul_w83(b[3], c8, e8);
   radix4(a);
   radix4(b);
 #pragma unroll
@@ -88,24 +94,21 @@ __device__ __forceinline__ void hput(double2 *h, int idx, double x, double y) {
 // Move the 8 values of this thread to positions wpos(q) and read back the
 // values at rpos(r) = j + r M/8, in two 16-byte rounds.  Element i of the
 // buffer lives at h[lpad(i) << lis].
-template <bool WAVE, class W>
-__device__ __forceinline__ void exchange8(ci v[8], int j, int M8, double2 *h, int lis, W wpos) {
+template <bool WAVE, class E, class W>
+__device__ __forceinline__ void exchange8(E v[8], int j, int M8, double2 *h, int lis, W wpos) {
   double2 t[8];
   xsync<WAVE>();
 #pragma unroll
-  for (int q = 0; q < 8; ++q) hput(h, lpad(wpos(q)) << lis, v[q].rn, v[q].rh);
+  for (int q = 0; q < 8; ++q) h[lpad(wpos(q)) << lis] = e_word0(v[q]);
   xsync<WAVE>();
 #pragma unroll
   for (int r = 0; r < 8; ++r) t[r] = h[lpad(j + r * M8) << lis];
   xsync<WAVE>();
 #pragma unroll
-  for (int q = 0; q < 8; ++q) hput(h, lpad(wpos(q)) << lis, v[q].in, v[q].ih);
+  for (int q = 0; q < 8; ++q) h[lpad(wpos(q)) << lis] = e_word1(v[q]);
   xsync<WAVE>();
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const double2 u = h[lpad(j + r * M8) << lis];
-    v[r] = ci{t[r].x, t[r].y, u.x, u.y};
-  }
+  for (int r = 0; r < 8; ++r) e_from_words(v[r], t[r], h[lpad(j + r * M8) << lis]);
 }
 
 // Forward interval DFT of the group's M = 2^LOGM elements (LOGM >= 3), a
@@ -114,8 +117,8 @@ __device__ __forceinline__ void exchange8(ci v[8], int j, int M8, double2 *h, in
 // half-element exchange buffer; element i lives at h[lpad(i) << lis].  With
 // WAVE the group must be exactly the lanes of (part of) one wavefront;
 // otherwise every thread of the workgroup must call this with the same M.
-template <int LOGM, bool WAVE, bool PF = false, class TT = twtab>
-__device__ __forceinline__ void fft8_group(ci v[8], int j, double2 *h, int lis, const TT &T) {
+template <int LOGM, bool WAVE, bool PF = false, class TT = twtab, class E = ci>
+__device__ __forceinline__ void fft8_group(E v[8], int j, double2 *h, int lis, const TT &T) {
   static_assert(LOGM >= 3, "length-8 groups at least");
   constexpr int M8 = 1 << (LOGM - 3);
   constexpr int FIRST = LOGM % 3;           // radix-2 (1) or radix-4 (2) first stage, or none (0)
@@ -135,11 +138,11 @@ __device__ __forceinline__ void fft8_group(ci v[8], int j, double2 *h, int lis, 
   if (FIRST == 1) {
     // radix 2 (Ns = 1): this thread acts for positions jv = j + t M/8, t < 4,
     // pairs (x[jv], x[jv + M/2]) = (v_t, v_{t+4}); results to y[2 jv], y[2 jv + 1].
-    ci y[8];
+    E y[8];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      y[2 * t] = ci_add(v[t], v[t + 4]);
-      y[2 * t + 1] = ci_sub(v[t], v[t + 4]);
+      y[2 * t] = e_add(v[t], v[t + 4]);
+      y[2 * t + 1] = e_sub(v[t], v[t + 4]);
     }
     exchange8<WAVE>(y, j, M8, h, lis, [&](int q) { return 2 * (j + (q >> 1) * M8) + (q & 1); });
 #pragma unroll
@@ -147,10 +150,10 @@ __device__ __forceinline__ void fft8_group(ci v[8], int j, double2 *h, int lis, 
   } else if (FIRST == 2) {
     // radix 4 (Ns = 1): positions jv = j + t M/8, t < 2, elements
     // x[jv + s M/4] = v_{t + 2 s}; results to y[4 jv + q].
-    ci y[8];
+    E y[8];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      ci u[4] = {v[t], v[t + 2], v[t + 4], v[t + 6]};
+      E u[4] = {v[t], v[t + 2], v[t + 4], v[t + 6]};
       radix4(u);
 #pragma unroll
       for (int q = 0; q < 4; ++q) y[4 * t + q] = u[q];
@@ -171,9 +174,9 @@ __device__ __forceinline__ void fft8_group(ci v[8], int j, double2 *h, int lis, 
       // and so do the stored points (rounded to nearest from the same side)
 #pragma unroll
       for (int r = 1; r < 8; ++r)
-        v[r] = r <= 2 ? ci_twiddle_q1(v[r], w[r].x, w[r].y, T.e)
-             : r <= 4 ? ci_twiddle_uh(v[r], w[r].x, w[r].y, T.e)
-                      : ci_twiddle(v[r], w[r].x, w[r].y, T.e);
+        v[r] = r <= 2 ? e_tw_q1(v[r], w[r].x, w[r].y, T.e)
+             : r <= 4 ? e_tw_uh(v[r], w[r].x, w[r].y, T.e)
+                      : e_tw(v[r], w[r].x, w[r].y, T.e);
     }
     radix8(v, c8, e8);
     if (st + 1 == NR8) break;  // last stage: X[j + q M/8] = v[q]
@@ -185,24 +188,21 @@ __device__ __forceinline__ void fft8_group(ci v[8], int j, double2 *h, int lis, 
 
 // Exchange of 4 values per thread (M = 4 M4 elements): write result q to
 // position wpos(q), read back x[j + r M4]; two 16-byte rounds, padded slots.
-template <bool WAVE, class W>
-__device__ __forceinline__ void exchange4(ci v[4], int j, int M4, double2 *h, W wpos) {
+template <bool WAVE, class E, class W>
+__device__ __forceinline__ void exchange4(E v[4], int j, int M4, double2 *h, W wpos) {
   double2 t[4];
   xsync<WAVE>();
 #pragma unroll
-  for (int q = 0; q < 4; ++q) hput(h, lpad(wpos(q)), v[q].rn, v[q].rh);
+  for (int q = 0; q < 4; ++q) h[lpad(wpos(q))] = e_word0(v[q]);
   xsync<WAVE>();
 #pragma unroll
   for (int r = 0; r < 4; ++r) t[r] = h[lpad(j + r * M4)];
   xsync<WAVE>();
 #pragma unroll
-  for (int q = 0; q < 4; ++q) hput(h, lpad(wpos(q)), v[q].in, v[q].ih);
+  for (int q = 0; q < 4; ++q) h[lpad(wpos(q))] = e_word1(v[q]);
   xsync<WAVE>();
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const double2 u = h[lpad(j + r * M4)];
-    v[r] = ci{t[r].x, t[r].y, u.x, u.y};
-  }
+  for (int r = 0; r < 4; ++r) e_from_words(v[r], t[r], h[lpad(j + r * M4)]);
 }
 
 // Forward interval DFT of M = 2^LOGM elements held 4 per thread by M/4
@@ -210,8 +210,8 @@ __device__ __forceinline__ void exchange4(ci v[4], int j, int M4, double2 *h, W 
 // Stockham radix-4 stages (one radix-2 stage first when LOGM is odd), same
 // conventions as fft8_group; the twiddles omega_{4 Ns}^{r k}, k < Ns, lie in
 // the first quadrant for r = 1, the upper half plane for r = 2.
-template <int LOGM, bool WAVE, class TT = twtab>
-__device__ __forceinline__ void fft4_group(ci v[4], int j, double2 *h, const TT &T) {
+template <int LOGM, bool WAVE, class TT = twtab, class E = ci>
+__device__ __forceinline__ void fft4_group(E v[4], int j, double2 *h, const TT &T) {
   static_assert(LOGM >= 2, "length-4 groups at least");
   constexpr int M4 = 1 << (LOGM - 2);
   constexpr int FIRST = LOGM % 2;
@@ -219,11 +219,11 @@ __device__ __forceinline__ void fft4_group(ci v[4], int j, double2 *h, const TT 
   if (FIRST == 1) {
     // radix 2 (Ns = 1): positions jv = j + t M/4 (t < 2) pair x[jv] = v_t with
     // x[jv + M/2] = v_{t+2}; results to y[2 jv], y[2 jv + 1]
-    ci y[4];
+    E y[4];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      y[2 * t] = ci_add(v[t], v[t + 2]);
-      y[2 * t + 1] = ci_sub(v[t], v[t + 2]);
+      y[2 * t] = e_add(v[t], v[t + 2]);
+      y[2 * t + 1] = e_sub(v[t], v[t + 2]);
     }
     exchange4<WAVE>(y, j, M4, h, [&](int q) { return 2 * (j + (q >> 1) * M4) + (q & 1); });
 #pragma unroll
@@ -238,9 +238,9 @@ __device__ __forceinline__ void fft4_group(ci v[4], int j, double2 *h, const TT 
       const double2 w1 = root(T, logNs + 2, static_cast<uint32_t>(k));
       const double2 w2 = root(T, logNs + 2, static_cast<uint32_t>(2 * k));
       const double2 w3 = root(T, logNs + 2, static_cast<uint32_t>(3 * k));
-      v[1] = ci_twiddle_q1(v[1], w1.x, w1.y, T.e);
-      v[2] = ci_twiddle_uh(v[2], w2.x, w2.y, T.e);
-      v[3] = ci_twiddle(v[3], w3.x, w3.y, T.e);
+      v[1] = e_tw_q1(v[1], w1.x, w1.y, T.e);
+      v[2] = e_tw_uh(v[2], w2.x, w2.y, T.e);
+      v[3] = e_tw(v[3], w3.x, w3.y, T.e);
     }
     radix4(v);
     if (st + 1 == NR4) break;  // X[j + q M/4] = v[q]

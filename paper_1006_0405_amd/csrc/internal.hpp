@@ -63,6 +63,7 @@ struct launch_cfg {
   int pack;    // 1: one complex transform of a + i b; 0: one transform per operand
   int persist; // 1: persistent row-pair pass with next-item prefetch (pack, rows <= 2^9)
   int icols;   // columns per workgroup in the inverse column pass
+  int disc;    // 1: FP64 midpoint-radius discs instead of rectangles (packed, plain row pass)
 };
 
 struct twtab_host {

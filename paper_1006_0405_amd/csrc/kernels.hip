@@ -237,6 +237,23 @@ __device__ __forceinline__ ci separated_product(const ci &Z, const ci &W) {
                      to_mrad(D.in, D.ih, 0.5), to_mrad(D.rh, D.rn, 0.5));
 }
 
+// The same for discs: S = Z + W and D = Z - W, A = S/2 and B = -i D/2 (exact
+// scalings and a permutation), C = A B.
+__device__ __forceinline__ md separated_product(const md &Z, const md &W) {
+  const md S = md_add(Z, W), D = md_sub(Z, W);
+  return md_mul(md{0.5 * S.re, 0.5 * S.im, 0.5 * S.r}, md{0.5 * D.im, -0.5 * D.re, 0.5 * D.r});
+}
+
+// A product's packed input element a + i b from two digits, thin.
+__device__ __forceinline__ void e_thin_pair(ci &z, double da, double db) { z = ci{-da, da, -db, db}; }
+__device__ __forceinline__ void e_thin_pair(md &z, double da, double db) { z = md{da, db, 0.0}; }
+
+// Real-part and imaginary-part enclosures (negated lower bound, upper bound).
+__device__ __forceinline__ double2 e_re_nh(const ci &z) { return make_double2(z.rn, z.rh); }
+__device__ __forceinline__ double2 e_im_nh(const ci &z) { return make_double2(z.in, z.ih); }
+__device__ __forceinline__ double2 e_re_nh(const md &z) { return make_double2(md_re_n(z), md_re_h(z)); }
+__device__ __forceinline__ double2 e_im_nh(const md &z) { return make_double2(md_im_n(z), md_im_h(z)); }
+
 // ---------------------------------------------------------------------------
 // k_small: the whole product in one workgroup of N/8 threads, N = 2^log_n,
 // 2^9 <= N <= 2^12.  LDS: N half-elements (16 B) for the exchanges, reused for
@@ -411,13 +428,14 @@ __global__ __launch_bounds__(512) void k_small(const task *tasks, int mode, int 
 // entries: the two factors come from 2^(log_n - h) and 2^h contiguous entries,
 // which stay cache-resident, instead of one scattered read over all N entries.
 // The product's error has one bound for every pair (pass_tw_bound).
-__device__ __forceinline__ ci apply_pass_tw(const ci &v, const twtab &T, uint32_t a, uint32_t b,
-                                            int log_n) {
+template <class E>
+__device__ __forceinline__ E apply_pass_tw(const E &v, const twtab &T, uint32_t a, uint32_t b,
+                                           int log_n) {
   const uint32_t t = (a * b) & ((1u << log_n) - 1u);
   const int h = (log_n + 1) >> 1;
   // omega_N^t = omega_{N / 2^h}^{t >> h} * omega_N^{t mod 2^h}
   const double2 w = tw_point_product(root(T, log_n - h, t >> h), root(T, log_n, t & ((1u << h) - 1u)));
-  return ci_twiddle(v, w.x, w.y, pass_tw_bound(T.e));
+  return e_tw(v, w.x, w.y, pass_tw_bound(T.e));
 }
 
 
@@ -450,17 +468,32 @@ struct mr_raw {
 __device__ __forceinline__ mr_raw mr_load_raw(const mrbuf &b, size_t idx) {
   return mr_raw{gload(b.m + idx), gload(b.r + idx)};
 }
-__device__ __forceinline__ ci mr_decode(const mr_raw &x) {
-  const double r = __longlong_as_double(static_cast<long long>(static_cast<unsigned long long>(x.r) << 32));
-  return ci{ru_sub(r, x.m.x), ru_add(x.m.x, r), ru_sub(r, x.m.y), ru_add(x.m.y, r)};
+// A disc is stored as it is (only its radius rounded up to 32 bits).
+__device__ __forceinline__ double mr_radius(uint32_t w) {
+  return __longlong_as_double(static_cast<long long>(static_cast<unsigned long long>(w) << 32));
 }
-__device__ __forceinline__ ci mr_load(const mrbuf &b, size_t idx) { return mr_decode(mr_load_raw(b, idx)); }
-__device__ __forceinline__ void mr_store(const mrbuf &b, size_t idx, const ci &v) {
-  const double mre = ru_mul(0.5, ru_sub(v.rh, v.rn)), mim = ru_mul(0.5, ru_sub(v.ih, v.in));
-  const double r = dmax(dmax(ru_sub(v.rh, mre), ru_add(v.rn, mre)), dmax(ru_sub(v.ih, mim), ru_add(v.in, mim)));
+__device__ __forceinline__ void mr_decode(const mr_raw &x, ci &z) {
+  const double r = mr_radius(x.r);
+  z = ci{ru_sub(r, x.m.x), ru_add(x.m.x, r), ru_sub(r, x.m.y), ru_add(x.m.y, r)};
+}
+__device__ __forceinline__ void mr_decode(const mr_raw &x, md &z) { z = md{x.m.x, x.m.y, mr_radius(x.r)}; }
+template <class E> __device__ __forceinline__ E mr_load(const mrbuf &b, size_t idx) {
+  E z;
+  mr_decode(mr_load_raw(b, idx), z);
+  return z;
+}
+__device__ __forceinline__ void mr_put(const mrbuf &b, size_t idx, double mre, double mim, double r) {
   const unsigned long long bits = static_cast<unsigned long long>(__double_as_longlong(r)) + 0xFFFFFFFFull;
   gstore(b.m + idx, d2v{mre, mim});
   gstore(b.r + idx, static_cast<uint32_t>(bits >> 32));
+}
+__device__ __forceinline__ void mr_store(const mrbuf &b, size_t idx, const ci &v) {
+  const double mre = ru_mul(0.5, ru_sub(v.rh, v.rn)), mim = ru_mul(0.5, ru_sub(v.ih, v.in));
+  const double r = dmax(dmax(ru_sub(v.rh, mre), ru_add(v.rn, mre)), dmax(ru_sub(v.ih, mim), ru_add(v.in, mim)));
+  mr_put(b, idx, mre, mim, r);
+}
+__device__ __forceinline__ void mr_store(const mrbuf &b, size_t idx, const md &v) {
+  mr_put(b, idx, v.re, v.im, v.r);
 }
 
 // Half-length inverse of a spectrum Z whose inverse transform x is real (the
@@ -472,10 +505,11 @@ __device__ __forceinline__ void mr_store(const mrbuf &b, size_t idx, const ci &v
 // Q = conj Z_{k+N/2}:  conj U_k = (P + Q) - i omega_N^k (P - Q).  An enclosure
 // of y is one of x: its real part encloses x_{2m} and its imaginary part
 // x_{2m+1}, because the exact x is real.
-__device__ __forceinline__ ci half_inverse_input(const ci &P, const ci &Q, const twtab &T,
-                                                 uint32_t k, int log_n) {
-  const ci t = apply_pass_tw(ci_sub(P, Q), T, k, 1u, log_n);
-  return ci_add(ci_add(P, Q), ci_mul_negi(t));
+template <class E>
+__device__ __forceinline__ E half_inverse_input(const E &P, const E &Q, const twtab &T, uint32_t k,
+                                                int log_n) {
+  const E t = apply_pass_tw(e_sub(P, Q), T, k, 1u, log_n);
+  return e_add(e_add(P, Q), e_mul_negi(t));
 }
 
 // Row k1 of the half-length inverse: v[r] holds P at k2 = j + r N2/8 (r < 8),
@@ -484,20 +518,20 @@ __device__ __forceinline__ ci half_inverse_input(const ci &P, const ci &Q, const
 // inter-pass twiddle of the length-N/2 four-step inverse, omega_{N/2}^{n2 k1},
 // and stores the N2/2 results at the start of the row.  `h` is the row's
 // exchange buffer (N2/2 elements), TF the table the row DFT reads.
-template <int LOG_N2, bool WAVE, class TT>
-__device__ __forceinline__ void half_inverse_row(const ci v[8], int j, uint32_t k1, int log_n1,
+template <int LOG_N2, bool WAVE, class TT, class E>
+__device__ __forceinline__ void half_inverse_row(const E v[8], int j, uint32_t k1, int log_n1,
                                                  double2 *h, const TT &TF, const twtab &T,
                                                  const mrbuf &Y) {
   constexpr int M8 = 1 << (LOG_N2 - 3);
   const int log_n = log_n1 + LOG_N2;
-  ci u[4];
+  E u[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     u[r] = half_inverse_input(v[r], v[r + 4], T, k1 + (static_cast<uint32_t>(j + r * M8) << log_n1),
                               log_n);
   fft4_group<LOG_N2 - 1, WAVE>(u, j, h, TF);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) u[q] = ci_conj(apply_pass_tw(u[q], T, j + q * M8, k1, log_n - 1));
+  for (int q = 0; q < 4; ++q) u[q] = e_conj(apply_pass_tw(u[q], T, j + q * M8, k1, log_n - 1));
   stores_after_loads();
   const size_t row = static_cast<size_t>(k1) << LOG_N2;
 #pragma unroll
@@ -531,7 +565,8 @@ __device__ __forceinline__ void reset_product_state(const task &tk) {
 // of a workgroup are adjacent in memory.  grid = (N2 / C, 1 (packed) or 2, tasks).
 // The packing and the digit size are compile-time (14% fewer instructions than
 // run-time flags: the digit loads then need no branches).
-template <int LOG_N1, int pack, int bits>
+// E: the element type, rectangles (ci) or discs (md, packed transforms only).
+template <int LOG_N1, int pack, int bits, class E>
 __global__ __launch_bounds__(512) void k_col_fwd(const task *tasks, int log_n2, int lc, twtab T) {
   extern __shared__ double2 hbuf[];
   const uint32_t z = enter_round_up();
@@ -552,13 +587,13 @@ __global__ __launch_bounds__(512) void k_col_fwd(const task *tasks, int log_n2, 
     ra[r] = load_digit(pack ? tk.a : p, pack ? tk.nda : nd, idx[r], bits);
     if (pack) rb[r] = load_digit(tk.b, tk.ndb, idx[r], bits);
   }
-  ci v[8];
+  E v[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    if (pack) {  // z = a + i b: both real operands in one complex transform
+    if constexpr (pack != 0) {  // z = a + i b: both real operands in one complex transform
       const double da = digit_value(ra[r], tk.nda, idx[r], bits);
       const double db = digit_value(rb[r], tk.ndb, idx[r], bits);
-      v[r] = ci{-da, da, -db, db};
+      e_thin_pair(v[r], da, db);
     } else {
       v[r] = ci_thin_real(digit_value(ra[r], nd, idx[r], bits));
     }
@@ -586,8 +621,8 @@ __device__ __forceinline__ void row_body(const task &tk, int log_n1, int R, cons
   ci va[8], vb[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    va[r] = mr_load(mr_of(tk.ya, log_n), row + j + r * M8);
-    vb[r] = mr_load(mr_of(tk.yb, log_n), row + j + r * M8);
+    va[r] = mr_load<ci>(mr_of(tk.ya, log_n), row + j + r * M8);
+    vb[r] = mr_load<ci>(mr_of(tk.yb, log_n), row + j + r * M8);
   }
   fft8_group<LOG_N2, WAVE>(va, j, hg, 0, T);
   fft8_group<LOG_N2, WAVE>(vb, j, hg, 0, T);
@@ -613,7 +648,7 @@ __global__ __launch_bounds__(512) void k_row(const task *tasks, int log_n1, int 
 // N2/8 threads.  Per row: forward length-N2 DFT, separated pointwise product
 // with the partner row, then the row step of the half-length inverse
 // (half_inverse_row).  grid = (N1 / 2 / G, tasks).
-template <int LOG_N2, bool WAVE>
+template <int LOG_N2, bool WAVE, class E>
 __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G, const twtab &T,
                                               double2 *hbuf) {
   const int log_n = log_n1 + LOG_N2;
@@ -630,9 +665,9 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
   double2 *hown = hbuf + static_cast<size_t>(rg) * rowslots;
   double2 *hpart = self ? hown : hbuf + static_cast<size_t>(rg ^ 1) * rowslots;
   const size_t row = static_cast<size_t>(k1) << LOG_N2;
-  ci v[8];
+  E v[8];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) v[r] = mr_load(mr_of(tk.ya, log_n), row + j + r * M8);
+  for (int r = 0; r < 8; ++r) v[r] = mr_load<E>(mr_of(tk.ya, log_n), row + j + r * M8);
   fft8_group<LOG_N2, WAVE, true>(v, j, hown, 0, T);
   // partner values, real halves then imaginary halves (workgroup barriers:
   // the partner row may be another wavefront)
@@ -645,25 +680,25 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
   double2 pr[8];
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 8; ++r) hown[lpad(j + r * M8)] = make_double2(v[r].rn, v[r].rh);
+  for (int r = 0; r < 8; ++r) hown[lpad(j + r * M8)] = e_word0(v[r]);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < 8; ++r) pr[r] = hpart[lpad(src[r])];
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 8; ++r) hown[lpad(j + r * M8)] = make_double2(v[r].in, v[r].ih);
+  for (int r = 0; r < 8; ++r) hown[lpad(j + r * M8)] = e_word1(v[r]);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const double2 pi = hpart[lpad(src[r])];
-    const ci W{pr[r].x, pr[r].y, pi.y, pi.x};  // conj(Z_{-k})
-    v[r] = ci_conj(separated_product(v[r], W));
+    E Zm;  // Z_{-k}
+    e_from_words(Zm, pr[r], hpart[lpad(src[r])]);
+    v[r] = e_conj(separated_product(v[r], e_conj(Zm)));
   }
   __syncthreads();  // the partner has read this row's buffer
   half_inverse_row<LOG_N2, WAVE>(v, j, k1, log_n1, hown, T, T, mr_of(tk.ya, log_n));
 }
 
-template <int LOG_N2>
+template <int LOG_N2, class E>
 // Three waves per SIMD: the register budget is capped at 168 (a few values spill
 // to scratch for the longest rows), which measured faster than two waves.
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k_row_pair(const task *tasks, int log_n1, int G, twtab T) {
@@ -671,7 +706,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
   const uint32_t z = enter_round_up();
   const task tk = after_mode(tasks, z)[gridDim.y - 1 - blockIdx.y];  // last written first
   T.tab = after_mode(T.tab, z);
-  row_pair_body<LOG_N2, (LOG_N2 <= 9)>(tk, log_n1, G, T, hbuf);
+  row_pair_body<LOG_N2, (LOG_N2 <= 9), E>(tk, log_n1, G, T, hbuf);
 }
 
 // Persistent form of k_row_pair for rows of at most 2^9 points: gridDim.x
@@ -718,7 +753,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
   ci v[8];
   mr_raw nx[8];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) v[r] = mr_load(mr_of(tk->ya, log_n), (static_cast<size_t>(k1) << LOG_N2) + j + r * M8);
+  for (int r = 0; r < 8; ++r) v[r] = mr_load<ci>(mr_of(tk->ya, log_n), (static_cast<size_t>(k1) << LOG_N2) + j + r * M8);
   for (;;) {
     const uint32_t nit = it + gridDim.x;
     const bool more = nit < total;
@@ -765,7 +800,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     k1 = nk1;
     self = nself;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = mr_decode(nx[r]);
+    for (int r = 0; r < 8; ++r) mr_decode(nx[r], v[r]);
   }
 }
 
@@ -774,7 +809,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
 // column n2 < N2/2 gives y_{n2 + (N2/2) n1} = x_{2 m} + i x_{2 m + 1} with
 // 2 m = N2 n1 + 2 n2, and each part is certified as one coefficient.
 // grid = (N2 / 2 / C, tasks).
-template <int LOG_N1>
+template <int LOG_N1, class E>
 __global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n2, int lc, int mode,
                                                  twtab T, double *dbg) {
   extern __shared__ double2 hbuf[];
@@ -787,11 +822,11 @@ __global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n2, 
   const int c = threadIdx.x & ((1 << lc) - 1), j = threadIdx.x >> lc;
   const uint32_t n2 = (xcd_group(blockIdx.x, gridDim.x) << lc) + c;
   if (threadIdx.x == 0) sh = cert_shared{0ull, 0ull, 0u, 0u};
-  ci v[8];
+  E v[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const uint32_t k1 = j + r * M8;
-    v[r] = ci_conj(mr_load(mr_of(tk.ya, log_n), (static_cast<size_t>(k1) << log_n2) + n2));
+    v[r] = e_conj(mr_load<E>(mr_of(tk.ya, log_n), (static_cast<size_t>(k1) << log_n2) + n2));
   }
   fft8_group<LOG_N1, false>(v, j, hbuf + c, lc, T);
   const double scale = ldexp(1.0, -log_n);
@@ -800,13 +835,14 @@ __global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n2, 
   for (int q = 0; q < 8; ++q) {
     const uint32_t n1 = j + q * M8;
     const uint32_t i = (n1 << log_n2) + 2 * n2;
-    const ci w = ci_scale(ci_conj(v[q]), scale);
+    const E w = e_scale(e_conj(v[q]), scale);
+    const double2 re = e_re_nh(w), im = e_im_nh(w);
     if (dbg != nullptr && blockIdx.y == 0) {
-      dbg_store(dbg, i, ci{w.rn, w.rh, 0.0, 0.0});
-      dbg_store(dbg, i + 1, ci{w.in, w.ih, 0.0, 0.0});
+      dbg_store(dbg, i, ci{re.x, re.y, 0.0, 0.0});
+      dbg_store(dbg, i + 1, ci{im.x, im.y, 0.0, 0.0});
     }
-    const unsigned long long c0 = certify_re(w.rn, w.rh, true, i, tk.L, mode, acc);
-    const unsigned long long c1 = certify_re(w.in, w.ih, true, i + 1, tk.L, mode, acc);
+    const unsigned long long c0 = certify_re(re.x, re.y, true, i, tk.L, mode, acc);
+    const unsigned long long c1 = certify_re(im.x, im.y, true, i + 1, tk.L, mode, acc);
     if (i + 1 < tk.L) {
       u64x2 pair;
       pair.x = c0;
@@ -1048,10 +1084,12 @@ hipError_t set_kernel_attributes() {
       SSA_SMALL_LENGTHS(SSA_K_SMALL)
 #undef SSA_K_SMALL
 #define SSA_K_PASS(L)                                                                    \
-  reinterpret_cast<const void *>(&k_col_fwd<L, 1, 8>), reinterpret_cast<const void *>(&k_col_fwd<L, 1, 4>), \
-      reinterpret_cast<const void *>(&k_col_fwd<L, 0, 8>), reinterpret_cast<const void *>(&k_col_fwd<L, 0, 4>), \
+  reinterpret_cast<const void *>(&k_col_fwd<L, 1, 8, ci>), reinterpret_cast<const void *>(&k_col_fwd<L, 1, 4, ci>), \
+      reinterpret_cast<const void *>(&k_col_fwd<L, 0, 8, ci>), reinterpret_cast<const void *>(&k_col_fwd<L, 0, 4, ci>), \
+      reinterpret_cast<const void *>(&k_col_fwd<L, 1, 8, md>), reinterpret_cast<const void *>(&k_col_fwd<L, 1, 4, md>), \
       reinterpret_cast<const void *>(&k_row<L>), \
-      reinterpret_cast<const void *>(&k_row_pair<L>), reinterpret_cast<const void *>(&k_col_inv<L>), \
+      reinterpret_cast<const void *>(&k_row_pair<L, ci>), reinterpret_cast<const void *>(&k_col_inv<L, ci>), \
+      reinterpret_cast<const void *>(&k_row_pair<L, md>), reinterpret_cast<const void *>(&k_col_inv<L, md>), \
       reinterpret_cast<const void *>(&k_fft_col<L>), reinterpret_cast<const void *>(&k_fft_row<L>),
       SSA_PASS_LENGTHS(SSA_K_PASS)
 #undef SSA_K_PASS
@@ -1149,22 +1187,27 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
   const int lc = log2_int(cfg.cols);
   const twtab T = to_dev(tw);
   if (l1 < 6 || l1 > 11 || l2 < 6 || l2 > 11 || (1 << lc) != cfg.cols) return hipErrorInvalidValue;
+  if (cfg.disc && (!cfg.pack || cfg.persist)) return hipErrorInvalidValue;  // discs: packed, plain row pass
   {
     const int threads = cfg.cols * static_cast<int>(N1 / 8);
     const size_t lds = sizeof(double2) * lpad_size(N1) * cfg.cols;
     const dim3 grid(N2 / cfg.cols, cfg.pack ? 1 : 2, ntasks);
     mark(hk, KIND_COL_FWD, 0);
     switch (l1) {
-#define SSA_L(L)                                                                                 \
-  case L:                                                                                        \
-    if (cfg.pack && digit_bits == 8)                                                             \
-      hipLaunchKernelGGL((k_col_fwd<L, 1, 8>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
-    else if (cfg.pack)                                                                           \
-      hipLaunchKernelGGL((k_col_fwd<L, 1, 4>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
-    else if (digit_bits == 8)                                                                    \
-      hipLaunchKernelGGL((k_col_fwd<L, 0, 8>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
-    else                                                                                         \
-      hipLaunchKernelGGL((k_col_fwd<L, 0, 4>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
+#define SSA_L(L)                                                                                     \
+  case L:                                                                                            \
+    if (cfg.disc && digit_bits == 8)                                                                 \
+      hipLaunchKernelGGL((k_col_fwd<L, 1, 8, md>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
+    else if (cfg.disc)                                                                               \
+      hipLaunchKernelGGL((k_col_fwd<L, 1, 4, md>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
+    else if (cfg.pack && digit_bits == 8)                                                            \
+      hipLaunchKernelGGL((k_col_fwd<L, 1, 8, ci>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
+    else if (cfg.pack)                                                                               \
+      hipLaunchKernelGGL((k_col_fwd<L, 1, 4, ci>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
+    else if (digit_bits == 8)                                                                        \
+      hipLaunchKernelGGL((k_col_fwd<L, 0, 8, ci>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
+    else                                                                                             \
+      hipLaunchKernelGGL((k_col_fwd<L, 0, 4, ci>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
     break;
       SSA_PASS_LENGTHS(SSA_L)
 #undef SSA_L
@@ -1203,7 +1246,10 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
     switch (l2) {
 #define SSA_L(L)                                                                                    \
   case L:                                                                                           \
-    hipLaunchKernelGGL(k_row_pair<L>, grid, dim3(threads), lds, s, d_tasks, l1, cfg.rows, T);      \
+    if (cfg.disc)                                                                                   \
+      hipLaunchKernelGGL((k_row_pair<L, md>), grid, dim3(threads), lds, s, d_tasks, l1, cfg.rows, T); \
+    else                                                                                            \
+      hipLaunchKernelGGL((k_row_pair<L, ci>), grid, dim3(threads), lds, s, d_tasks, l1, cfg.rows, T); \
     break;
       SSA_PASS_LENGTHS(SSA_L)
 #undef SSA_L
@@ -1238,8 +1284,12 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
     switch (l1) {
 #define SSA_L(L)                                                                                \
   case L:                                                                                       \
-    hipLaunchKernelGGL(k_col_inv<L>, grid, dim3(threads), lds, s, d_tasks, l2, lci, cert_mode, \
-                       T, dbg);                                                                 \
+    if (cfg.disc)                                                                               \
+      hipLaunchKernelGGL((k_col_inv<L, md>), grid, dim3(threads), lds, s, d_tasks, l2, lci,    \
+                         cert_mode, T, dbg);                                                    \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_col_inv<L, ci>), grid, dim3(threads), lds, s, d_tasks, l2, lci,    \
+                         cert_mode, T, dbg);                                                    \
     break;
       SSA_PASS_LENGTHS(SSA_L)
 #undef SSA_L
