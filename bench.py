@@ -283,16 +283,17 @@ def measure_singles(binding, torch, reps=10):
     return out
 
 
-def measure_reach(binding, torch):
-    """How far the FP64 rectangular-interval path certifies base-256 products of
-    two equal-length operands (uniform random bytes, seed 2, and all-0xFF):
-    status and maximum enclosure radius per length, at the lengths where the
-    transform doubles.  A certified product is checked against CPython's integer
-    product (up to 2^19 bytes per operand, to bound the host time)."""
+def measure_reach(binding, torch, arithmetic="rect"):
+    """How far the FP64 path (rectangles, or discs with arithmetic="disc")
+    certifies base-256 products of two equal-length operands (uniform random
+    bytes, seed 2, and all-0xFF): status and maximum enclosure radius per
+    length, at the lengths where the transform doubles.  A certified product is
+    checked against CPython's integer product (up to 2^19 bytes per operand, to
+    bound the host time)."""
     from paper_1006_0405_amd.workloads import all_ff, pair
     out = []
     for n in (75_000, 1 << 17, 1 << 18, 1 << 19, 1 << 20, 1 << 21):
-        plan = binding.Plan(n, n)
+        plan = binding.Plan(n, n, arithmetic=arithmetic)
         for kind in ("random", "all_ff"):
             a, b = pair(2, n) if kind == "random" else (all_ff(n), all_ff(n))
             st, res = plan.mul(a, b)
@@ -304,6 +305,8 @@ def measure_reach(binding, torch):
             out.append({"operand_bytes": n, "fft_length": 1 << s["log_n"], "operands": kind,
                         "status": binding.STATUS_NAMES[st], "max_radius": s["max_radius"]})
         plan.close()
+    if arithmetic != "rect":
+        return out
     # the refused random product once more with base-16 refinement
     n = 1 << 20
     plan = binding.Plan(n, n, refine_digits=True)
@@ -317,6 +320,47 @@ def measure_reach(binding, torch):
     return out
 
 
+def measure_disc(binding, torch, A, Bs, steps, warmup):
+    """The timed workload (the same operands) with the three passes in FP64
+    discs (plan option arithmetic="disc"): autotuned shape, products checked,
+    graph launches timed like the main line, per-kernel times from eager
+    launches with HIP events."""
+    n = len(A[0])
+    plan = binding.Plan(n, n, arithmetic="disc")
+    log_n = binding.fft_size(n, n).bit_length() - 1
+    tuned = plan.autotune(log_n, count=len(A))
+    batch = binding.Batch(plan, A, Bs)
+    status = batch.run().cpu().numpy()
+    assert np.all(status == binding.SSA_OK), status
+    for i in range(len(A)):
+        want = (int.from_bytes(A[i].tobytes(), "little") *
+                int.from_bytes(Bs[i].tobytes(), "little")).to_bytes(2 * n, "little")
+        assert batch.OUT[i].cpu().numpy().tobytes() == want, "disc product %d is wrong" % i
+    max_rad = max(s["max_radius"] for s in batch.stats())
+    for _ in range(warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.run()
+    torch.cuda.synchronize()
+    rate = len(A) * steps / (time.perf_counter() - t0)
+    for _ in range(warmup):
+        batch.run_timed()
+    torch.cuda.synchronize()
+    batch.kernel_times()
+    for _ in range(steps):
+        batch.run_timed()
+    torch.cuda.synchronize()
+    kt = batch.kernel_times()
+    batch.close()
+    plan.close()
+    return {"products_per_s": rate, "max_radius": max_rad,
+            "launch_shape": {k: tuned[k] for k in ("log_n1", "cols", "rows", "persistent", "inv_cols")},
+            "kernel_ms_per_launch": {k: kt[k][0] / max(kt[k][1], 1)
+                                     for k in ("col_fwd", "row", "col_inv", "carry")}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -328,6 +372,8 @@ def main():
                     help="skip the 4096-product uneven batch (FP64 base 256 and base 16)")
     ap.add_argument("--no-singles", action="store_true",
                     help="skip the one-at-a-time products (1,024, 75,000 and 1,000,000 bytes)")
+    ap.add_argument("--no-disc", action="store_true",
+                    help="skip the same workload with the three passes in FP64 discs")
     ap.add_argument("--no-fft", action="store_true",
                     help="skip the standalone forward interval FFT (64 transforms of 2^18)")
     ap.add_argument("--separate-transforms", action="store_true",
@@ -490,10 +536,16 @@ def main():
     }
     batch.close()
     plan.close()
+    if not args.no_disc:
+        d = measure_disc(binding, torch, A, Bs, args.steps, args.warmup)
+        d["speedup_vs_rect"] = d["products_per_s"] / value
+        result["disc_fp64_2p18"] = d
 
     if not args.no_singles:
         result["single_products"] = measure_singles(binding, torch)
         result["fp64_reach_base256"] = measure_reach(binding, torch)
+        if not args.no_disc:
+            result["fp64_disc_reach_base256"] = measure_reach(binding, torch, "disc")
 
     if not args.no_fft:
         result["fft_forward_2p18"] = measure_fft(binding, torch, max(5, args.steps // 5))
