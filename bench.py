@@ -133,7 +133,8 @@ def fp64_rate(kinds, ms_per_launch):
     return out or None
 
 
-def measure_batch(binding, torch, digit_bits, steps, precision="fp64", A=None, B=None):
+def measure_batch(binding, torch, digit_bits, steps, precision="fp64", A=None, B=None,
+                  arithmetic="rect"):
     """Default: the 4096-product batch, operand lengths log-uniform in
     [64, 16384] bytes (seed 3).  One graph launch per step; every product
     checked once against CPython integers outside the timed region."""
@@ -141,7 +142,7 @@ def measure_batch(binding, torch, digit_bits, steps, precision="fp64", A=None, B
     if A is None:
         A, B = make_batch(seed=3)
     plan = binding.Plan(max(len(a) for a in A), max(len(b) for b in B), digit_bits=digit_bits,
-                        precision=precision)
+                        precision=precision, arithmetic=arithmetic)
     lengths = sorted({binding.fft_size(len(a), len(b), digit_bits).bit_length() - 1
                       for a, b in zip(A, B)})
     for lg in lengths:
@@ -172,6 +173,7 @@ def measure_batch(binding, torch, digit_bits, steps, precision="fp64", A=None, B
         "max_radius": max(s["max_radius"] for s in stats),
         "digit_bits": digit_bits,
         "precision": precision,
+        "arithmetic": arithmetic,
     }
     if precision != "fp64":
         n_try = sum(1 for s in stats if s["fp32_attempt"])
@@ -558,6 +560,10 @@ def main():
             r32["speedup_vs_fp64"] = r32["products_per_s"] / r64["products_per_s"]
             result["batch_fp64_" + base] = r64
             result["batch_fp32_fallback_" + base] = r32
+            if not args.no_disc:
+                rd = measure_batch(binding, torch, bits, steps, arithmetic="disc")
+                rd["speedup_vs_rect"] = rd["products_per_s"] / r64["products_per_s"]
+                result["batch_fp64_disc_" + base] = rd
         # inside the FP32 frontier: 8192 products of 100 x 100 bytes, base 16
         # (L = 399, N = 512), where every FP32 attempt is expected to certify
         from paper_1006_0405_amd.workloads import pair

@@ -76,14 +76,15 @@ typedef struct {
                               the same; stats.refined says which run produced it.
                               Batches report the base-256 outcome.                 */
   int arithmetic;          /* SSA_ARITH_RECT (default): rectangular complex intervals
-                              (section 2.5) everywhere.  SSA_ARITH_DISC: products of
-                              transform length above 2^12 run the three passes in
-                              FP64 midpoint-radius discs (circular containment sets,
+                              (section 2.5) everywhere.  SSA_ARITH_DISC: the FP64
+                              transforms, products and certification run in
+                              midpoint-radius discs (circular containment sets,
                               section 4), which a rotation by a root of unity does not
-                              enlarge; needs the packed transform (separate_transforms
-                              = 0; SSA_INVALID_ARGUMENT otherwise) and a launch shape
-                              without the persistent row pass.  Shorter products stay
-                              rectangular.  Same products.                        */
+                              enlarge; the FP32 attempt's forward transform is a disc
+                              transform either way.  Needs the packed transform
+                              (separate_transforms = 0; SSA_INVALID_ARGUMENT
+                              otherwise) and launch shapes without the persistent
+                              row pass.  Same products.                           */
 } ssa_plan_opts;
 
 typedef struct {

@@ -214,14 +214,15 @@ hipError_t enqueue_class(const ssa_plan *p, const task *d_tasks, int n, int n32,
   if (bits == 0) bits = p->opts.digit_bits;
   const int mode = p->force_too_wide ? CERT_FORCE_TOO_WIDE : p->opts.certify_mode;
   const int pack = p->opts.separate_transforms ? 0 : 1;
+  const int disc = p->opts.arithmetic == SSA_ARITH_DISC ? 1 : 0;
   if (log_n <= SMALL_MAX_LOG) {
     if (n32 == 0)
-      return launch_small(d_tasks, n, log_n, bits, mode, pack, 0, 0, 0, tw_of(p), dbg, s, hk);
+      return launch_small(d_tasks, n, log_n, bits, mode, pack, disc, 0, 0, 0, tw_of(p), dbg, s, hk);
     // FP32 attempt, then FP64 over the class except what the attempt certified
-    const hipError_t e =
-        launch_small(d_tasks, n32, log_n, bits, mode, pack, 1, 0, p->hooks, tw_of(p), dbg, s, hk);
+    const hipError_t e = launch_small(d_tasks, n32, log_n, bits, mode, pack, disc, 1, 0, p->hooks,
+                                      tw_of(p), dbg, s, hk);
     if (e != hipSuccess) return e;
-    return launch_small(d_tasks, n, log_n, bits, mode, pack, 0, 1, 0, tw_of(p), dbg, s, hk);
+    return launch_small(d_tasks, n, log_n, bits, mode, pack, disc, 0, 1, 0, tw_of(p), dbg, s, hk);
   }
   return launch_multipass(d_tasks, n, log_n, p->cfg[log_n], bits, mode, tw_of(p), dbg, s, hk);
 }

@@ -93,7 +93,7 @@ struct timing_hook {
 // fp32: FP32 first attempt over tasks that are all marked fp32; rerun: FP64
 // pass that follows it, skipping marked tasks that the attempt certified.
 hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bits, int cert_mode,
-                        int pack, int fp32, int rerun, int hooks, const twtab_host &tw,
+                        int pack, int disc, int fp32, int rerun, int hooks, const twtab_host &tw,
                         double *dbg, hipStream_t s, const timing_hook *hk = nullptr);
 hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const launch_cfg &cfg,
                             int digit_bits, int cert_mode, const twtab_host &tw, double *dbg,

@@ -259,60 +259,67 @@ __device__ __forceinline__ double2 e_im_nh(const md &z) { return make_double2(md
 // 2^9 <= N <= 2^12.  LDS: N half-elements (16 B) for the exchanges, reused for
 // the coefficients.
 
-template <int LOG_N, bool WAVE>
-__device__ __forceinline__ void small_body(const task &tk, int bits, int mode, int pack,
-                                           int fp32, int hooks, int rerun, const twtab &T,
-                                           double *dbg, double2 *h, cert_shared &sh,
-                                           uint32_t *sh_waves) {
+// An FP32 disc as an FP64 element (float to double is exact).
+__device__ __forceinline__ void mr_to_e(const mr &a, ci &z) { z = mr_to_ci(a); }
+__device__ __forceinline__ void mr_to_e(const mr &a, md &z) {
+  z = md{static_cast<double>(a.re), static_cast<double>(a.im), static_cast<double>(a.r)};
+}
+
+// E: rectangles (ci), or discs (md) for the packed transform.
+template <int LOG_N, bool WAVE, int PACK, class E>
+__device__ __forceinline__ void small_body(const task &tk, int bits, int mode, int fp32, int hooks,
+                                           int rerun, const twtab &T, double *dbg, double2 *h,
+                                           cert_shared &sh, uint32_t *sh_waves) {
   constexpr int M8 = 1 << (LOG_N - 3);
   constexpr uint32_t mask = (1u << LOG_N) - 1u;
   const int j = threadIdx.x;
-  ci va[8];
+  E va[8];
   uint32_t ra[8], rb[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     ra[r] = load_digit(tk.a, tk.nda, j + r * M8, bits);
     rb[r] = load_digit(tk.b, tk.ndb, j + r * M8, bits);
   }
-  if (pack) {  // one transform of z = a + i b, then separation
+  if constexpr (PACK != 0) {  // one transform of z = a + i b, then separation
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const double da = digit_value(ra[r], tk.nda, j + r * M8, bits);
       const double db = digit_value(rb[r], tk.ndb, j + r * M8, bits);
-      va[r] = ci{-da, da, -db, db};
+      e_thin_pair(va[r], da, db);
     }
-    if (fp32) {  // forward transform in FP32 discs, then back to double rectangles
+    if (fp32) {  // forward transform in FP32 discs, then back to FP64 elements
       mr w[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r)
-        w[r] = mr{static_cast<float>(va[r].rh), static_cast<float>(va[r].ih), 0.0f};
+        w[r] = mr{static_cast<float>(digit_value(ra[r], tk.nda, j + r * M8, bits)),
+                  static_cast<float>(digit_value(rb[r], tk.ndb, j + r * M8, bits)), 0.0f};
       mr_fft8_group<LOG_N, WAVE>(w, j, reinterpret_cast<float4 *>(h), T);
       const float extra = (hooks & HOOK_FORCE_FP32_FAIL) ? 1.0e9f : 0.0f;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         w[r].r += extra;
-        va[r] = mr_to_ci(w[r]);
+        mr_to_e(w[r], va[r]);
       }
     } else {
       fft8_group<LOG_N, WAVE>(va, j, h, 0, T);
     }
-    // partners Z_{-k}: real halves, then imaginary halves
+    // partners Z_{-k}: first words, then second words
     double2 pr[8];
     xsync<WAVE>();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) h[lpad(j + r * M8)] = make_double2(va[r].rn, va[r].rh);
+    for (int r = 0; r < 8; ++r) h[lpad(j + r * M8)] = e_word0(va[r]);
     xsync<WAVE>();
 #pragma unroll
     for (int r = 0; r < 8; ++r) pr[r] = h[lpad((0u - static_cast<uint32_t>(j + r * M8)) & mask)];
     xsync<WAVE>();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) h[lpad(j + r * M8)] = make_double2(va[r].in, va[r].ih);
+    for (int r = 0; r < 8; ++r) h[lpad(j + r * M8)] = e_word1(va[r]);
     xsync<WAVE>();
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      const double2 pi = h[lpad((0u - static_cast<uint32_t>(j + r * M8)) & mask)];
-      const ci W{pr[r].x, pr[r].y, pi.y, pi.x};  // conj(Z_{-k})
-      va[r] = ci_conj(separated_product(va[r], W));
+      E Zm;  // Z_{-k}
+      e_from_words(Zm, pr[r], h[lpad((0u - static_cast<uint32_t>(j + r * M8)) & mask)]);
+      va[r] = e_conj(separated_product(va[r], e_conj(Zm)));
     }
   } else {  // one transform per operand, pointwise product
     ci vb[8];
@@ -351,9 +358,11 @@ __device__ __forceinline__ void small_body(const task &tk, int bits, int mode, i
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const uint32_t i = j + r * M8;
-    const ci v = ci_scale(ci_conj(va[r]), scale);
-    if (dbg != nullptr && blockIdx.x == 0) dbg_store(dbg, i, v);
-    cv[r] = certify(v, i, tk.L, mode, acc);
+    const E v = e_scale(e_conj(va[r]), scale);
+    const double2 re = e_re_nh(v), im = e_im_nh(v);
+    if (dbg != nullptr && blockIdx.x == 0) dbg_store(dbg, i, ci{re.x, re.y, im.x, im.y});
+    // a real coefficient: the imaginary part must contain 0
+    cv[r] = certify_re(re.x, re.y, im.x >= 0.0 && im.y >= 0.0, i, tk.L, mode, acc);
   }
   cert_reduce(sh, acc);
   __syncthreads();  // LDS free again; counters final
@@ -398,7 +407,7 @@ __device__ __forceinline__ void small_body(const task &tk, int bits, int mode, i
 // marked products that the attempt certified return at once.  The decision is
 // read from the statistics on the device, so a captured launch sequence holds
 // the fallback unconditionally.
-template <int LOG_N, int bits, int pack>
+template <int LOG_N, int bits, int pack, class E>
 __global__ __launch_bounds__(512) void k_small(const task *tasks, int mode, int fp32, int rerun,
                                                int hooks, twtab T, double *dbg) {
   extern __shared__ double2 hbuf[];
@@ -410,8 +419,8 @@ __global__ __launch_bounds__(512) void k_small(const task *tasks, int mode, int 
   if (rerun && tk.fp32 != 0u && tk.st->too_wide == 0u && tk.st->internal == 0u) return;
   if (threadIdx.x == 0) sh = cert_shared{0ull, 0ull, 0u, 0u};
   __syncthreads();
-  small_body<LOG_N, (LOG_N <= 9)>(tk, bits, mode, pack, fp32, hooks, rerun, T, dbg, hbuf, sh,
-                                  sh_waves);
+  small_body<LOG_N, (LOG_N <= 9), pack, E>(tk, bits, mode, fp32, hooks, rerun, T, dbg, hbuf, sh,
+                                           sh_waves);
 }
 
 // ---------------------------------------------------------------------------
@@ -1079,8 +1088,9 @@ static constexpr int MAX_DYN_LDS = 131072;
 hipError_t set_kernel_attributes() {
   const void *ks[] = {
 #define SSA_K_SMALL(L)                                                                      \
-  reinterpret_cast<const void *>(&k_small<L, 8, 1>), reinterpret_cast<const void *>(&k_small<L, 4, 1>), \
-      reinterpret_cast<const void *>(&k_small<L, 8, 0>), reinterpret_cast<const void *>(&k_small<L, 4, 0>),
+  reinterpret_cast<const void *>(&k_small<L, 8, 1, ci>), reinterpret_cast<const void *>(&k_small<L, 4, 1, ci>), \
+      reinterpret_cast<const void *>(&k_small<L, 8, 0, ci>), reinterpret_cast<const void *>(&k_small<L, 4, 0, ci>), \
+      reinterpret_cast<const void *>(&k_small<L, 8, 1, md>), reinterpret_cast<const void *>(&k_small<L, 4, 1, md>),
       SSA_SMALL_LENGTHS(SSA_K_SMALL)
 #undef SSA_K_SMALL
 #define SSA_K_PASS(L)                                                                    \
@@ -1117,25 +1127,32 @@ static inline void mark(const timing_hook *hk, int kind, int phase) {
 }
 
 hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bits, int cert_mode,
-                        int pack, int fp32, int rerun, int hooks, const twtab_host &tw,
+                        int pack, int disc, int fp32, int rerun, int hooks, const twtab_host &tw,
                         double *dbg, hipStream_t s, const timing_hook *hk) {
   const int threads = 1 << (log_n - 3);
   const size_t lds = sizeof(double2) * lpad_size(size_t(1) << log_n);
+  if (disc && !pack) return hipErrorInvalidValue;  // discs: packed transform only
   mark(hk, KIND_SMALL, 0);
   switch (log_n) {
 #define SSA_L(L)                                                                               \
   case L:                                                                                      \
-    if (digit_bits == 8 && pack)                                                                \
-      hipLaunchKernelGGL((k_small<L, 8, 1>), dim3(ntasks), dim3(threads), lds, s, d_tasks,      \
+    if (disc && digit_bits == 8)                                                                \
+      hipLaunchKernelGGL((k_small<L, 8, 1, md>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
+                         cert_mode, fp32, rerun, hooks, to_dev(tw), dbg);                       \
+    else if (disc)                                                                              \
+      hipLaunchKernelGGL((k_small<L, 4, 1, md>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
+                         cert_mode, fp32, rerun, hooks, to_dev(tw), dbg);                       \
+    else if (digit_bits == 8 && pack)                                                           \
+      hipLaunchKernelGGL((k_small<L, 8, 1, ci>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
                          cert_mode, fp32, rerun, hooks, to_dev(tw), dbg);                       \
     else if (pack)                                                                              \
-      hipLaunchKernelGGL((k_small<L, 4, 1>), dim3(ntasks), dim3(threads), lds, s, d_tasks,      \
+      hipLaunchKernelGGL((k_small<L, 4, 1, ci>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
                          cert_mode, fp32, rerun, hooks, to_dev(tw), dbg);                       \
     else if (digit_bits == 8)                                                                   \
-      hipLaunchKernelGGL((k_small<L, 8, 0>), dim3(ntasks), dim3(threads), lds, s, d_tasks,      \
+      hipLaunchKernelGGL((k_small<L, 8, 0, ci>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
                          cert_mode, fp32, rerun, hooks, to_dev(tw), dbg);                       \
     else                                                                                        \
-      hipLaunchKernelGGL((k_small<L, 4, 0>), dim3(ntasks), dim3(threads), lds, s, d_tasks,      \
+      hipLaunchKernelGGL((k_small<L, 4, 0, ci>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
                          cert_mode, fp32, rerun, hooks, to_dev(tw), dbg);                       \
     break;
     SSA_SMALL_LENGTHS(SSA_L)

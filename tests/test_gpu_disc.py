@@ -1,11 +1,11 @@
 """GPU tests of the FP64 disc arithmetic (plan option arithmetic="disc").
 
-Products whose transform is longer than 2^12 run the three passes in FP64
-midpoint-radius discs, the circular containment sets of the paper's section 4,
-instead of rectangles.  The product must be the same exact integer: bit-exact
-against CPython's integers, the oracle (which works in rectangles, the paper's
-section 2.5) and the all-0xFF closed form; every enclosure must contain the
-exact convolution coefficient.  The disc and rectangle radii are reported side
+Every product runs its FP64 transforms in midpoint-radius discs, the circular
+containment sets of the paper's section 4, instead of rectangles: the
+single-workgroup products (N <= 2^12) and the three passes above.  The product
+must be the same exact integer: bit-exact against CPython's integers, the
+oracle (which works in rectangles, the paper's section 2.5) and the all-0xFF
+closed form; every enclosure must contain the exact convolution coefficient.  The disc and rectangle radii are reported side
 by side.
 """
 import numpy as np
@@ -144,6 +144,63 @@ def test_disc_batch_mixed_lengths_and_autotuner():
         assert np.array_equal(_np(bt.OUT[i]), int_product(A[i], B[i])), i
     bt.close()
     plan.close()
+
+
+@pytest.mark.parametrize("digit_bits", [8, 4])
+def test_disc_single_workgroup_products(digit_bits):
+    sizes = [(1, 1), (1, 2), (3, 5), (17, 33), (100, 100), (127, 2), (255, 256), (511, 512),
+             (1000, 1), (1023, 1025), (2048, 2048)]
+    plan = binding.Plan(2048, 2048, digit_bits=digit_bits, arithmetic="disc")
+    rect = binding.Plan(2048, 2048, digit_bits=digit_bits)
+    for s, (na, nb) in enumerate(sizes):
+        if digit_bits == 4 and na + nb > 2049:
+            continue
+        a, b = pair(900 + s, na, nb)
+        st, out = plan.mul(a, b)
+        assert st == binding.SSA_OK, (na, nb)
+        assert np.array_equal(_np(out), int_product(a, b)), (na, nb)
+        f = all_ff(na)
+        st, out = plan.mul(f, f)
+        assert st == binding.SSA_OK and np.array_equal(_np(out), int_product(f, f)), na
+        rd = plan.stats()["max_radius"]
+        rect.mul(f, f)
+        print("%d x %d all-0xFF: radius disc %.3g, rect %.3g" % (na, na, rd, rect.stats()["max_radius"]))
+    st, out, enc = plan.debug_enclosures(*pair(77, 1000, 900))
+    enc = _np(enc)
+    a, b = pair(77, 1000, 900)
+    c = exact_convolution(a, b) if digit_bits == 8 else exact_convolution(nibbles(a), nibbles(b))
+    assert st == binding.SSA_OK
+    assert np.all(enc[:len(c), 0] <= c) and np.all(c <= enc[:len(c), 1])
+    assert np.all(enc[:, 2] <= 0) and np.all(enc[:, 3] >= 0)
+    plan.close()
+    rect.close()
+
+
+@pytest.mark.parametrize("digit_bits", [8, 4])
+def test_disc_fp32_attempt_exact_and_fallback_counts(digit_bits):
+    """The FP32 attempt's forward transform (FP32 discs) followed by the FP64
+    product and inverse in discs instead of rectangles: products exact either
+    way; how many sizes certify without the FP64 re-run is printed for both."""
+    sizes = [(1, 1), (1, 2), (3, 5), (17, 33), (64, 65), (100, 100), (127, 2), (200, 57),
+             (255, 256), (300, 300), (511, 512), (1000, 1), (1023, 1025)]
+    used = {}
+    for arith in ("rect", "disc"):
+        plan = binding.Plan(2048, 2048, digit_bits=digit_bits, precision="fp32_fallback",
+                            arithmetic=arith)
+        plan.set_fp32_policy(4096)  # attempt FP32 on every single-workgroup product
+        used[arith] = []
+        for s, (na, nb) in enumerate(sizes):
+            if digit_bits == 4 and na + nb > 2049:
+                continue
+            a, b = pair(700 + s, na, nb)
+            st, out = plan.mul(a, b)
+            assert st == binding.SSA_OK, (arith, na, nb)
+            assert np.array_equal(_np(out), int_product(a, b)), (arith, na, nb)
+            assert plan.stats()["fp32_attempt"] == 1
+            used[arith].append(plan.stats()["fallback"])
+        plan.close()
+    print("FP32 attempts certified without re-run: rect %d, disc %d of %d" % (
+        used["rect"].count(0), used["disc"].count(0), len(used["rect"])))
 
 
 def test_disc_rejected_with_separate_transforms():
