@@ -110,6 +110,9 @@ def traffic_for(kernel, launches_products):
 
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak (an FMA counts two)
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per SIMD every
+# 4 cycles (16 lanes per SIMD; the same 16 FP64 FMA lanes give the 78.6 TFLOP/s)
+VALU_PEAK_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 
 
 def fp64_rate(kinds, ms_per_launch):
@@ -128,8 +131,12 @@ def fp64_rate(kinds, ms_per_launch):
         if k in d["kernels"] and ms_per_launch.get(k):
             fl = d["kernels"][k]["flops_per_launch"]
             tf = fl / (ms_per_launch[k] * 1e-3) / 1e12
+            valu = d["kernels"][k]["counters"]["SQ_INSTS_VALU"]
+            vr = valu / (ms_per_launch[k] * 1e-3)
             out[k] = {"flops_per_launch": fl, "tflops": tf, "peak": FP64_PEAK_TFLOPS,
-                      "frac": tf / FP64_PEAK_TFLOPS}
+                      "frac": tf / FP64_PEAK_TFLOPS,
+                      "valu_wave_instr_per_launch": valu,
+                      "valu_issue_frac": vr / VALU_PEAK_WAVE_INSTR_PER_S}
     return out or None
 
 
