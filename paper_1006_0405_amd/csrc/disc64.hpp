@@ -53,32 +53,38 @@ __device__ __forceinline__ md md_scale(const md &a, double p2) {
 // (|w - w*| <= sqrt(2) e < 1.5 e, |w*| = 1):
 //   |m' - w* a*| <= |m' - w m| + |w - w*| |m| + |w*| |m - a*|
 //               <= rounding + 1.5 e (|re| + |im|) + r.
-// m' = (RU(c re - RU(s im)), RU(s re + RU(c im))): four roundings, each within
-// 2^-52 of its result plus MD_ETA.
+// m' = (RU(c re - p), RU(s re + q)) with p = RU(s im), q = RU(c im): four
+// roundings, each within 2^-52 of its result plus MD_ETA, and the four results
+// sum to at most (1 + 2^-52)^2 (|c| + |s|) (|re| + 2 |im|) + 6 MD_ETA with
+// |c| + |s| <= sqrt(2) (1 + 1.5 e): below 2.9 (|re| + |im|) for e < 2^-20.  So
+//   r' = r + (1.5 e + 2.9 2^-52) (|re| + |im|) + 8 MD_ETA,
+// three operations instead of one per rounding.
 __device__ __forceinline__ md md_tw(const md &a, double c, double s, double e) {
   const double p = ru_mul(s, a.im), q = ru_mul(c, a.im);
   md z;
   z.re = ru_fms(c, a.re, p);
   z.im = ru_fma(s, a.re, q);
-  const double e15 = ru_mul(1.5, e);
-  const double t = ru_fma_ab(e15, a.re, ru_fma_ab(e15, a.im, ru_add(a.r, 4.0 * MD_ETA)));
-  z.r = ru_fma_ab(MD_U, z.re, ru_fma_ab(MD_U, z.im, ru_fma_ab(MD_U, p, ru_fma_ab(MD_U, q, t))));
+  const double k = ru_fma(1.5, e, 2.9 * MD_U);
+  z.r = ru_fma_ab(k, a.re, ru_fma_ab(k, a.im, ru_add(a.r, 8.0 * MD_ETA)));
   return z;
 }
 
 // Product of two discs: m' = (a.re b.re - a.im b.im, a.re b.im + a.im b.re)
-// with four roundings, and
+// with four roundings (p1 = RU(a.im b.im), p2 = RU(a.im b.re)), and
 //   |a* b* - m_a m_b| <= |m_a| r_b + r_a |m_b| + r_a r_b,
-// |m| <= |re| + |im|.
+// |m| <= |re| + |im|.  The four rounded results sum to at most
+// (1 + 2^-52)^2 2 ma mb' + 4 MD_ETA (ma = |a.re| + |a.im|, mb' = |b.re| + |b.im|),
+// so the roundings add at most 2.0001 2^-52 ma mb' + 5 MD_ETA:
+//   r' = ma (r_b + 2.0001 2^-52 mb') + r_a (mb' + r_b) + 8 MD_ETA.
 __device__ __forceinline__ md md_mul(const md &a, const md &b) {
   const double p1 = ru_mul(a.im, b.im), p2 = ru_mul(a.im, b.re);
   md z;
   z.re = ru_fms(a.re, b.re, p1);
   z.im = ru_fma(a.re, b.im, p2);
-  const double ma = ru_add_aa(a.re, dabs(a.im));            // |a.re| + |a.im|
-  const double mb = ru_add_aa(b.re, ru_add_aa(b.im, b.r));  // |b.re| + |b.im| + r_b
-  const double t = ru_fma(ma, b.r, ru_fma(a.r, mb, 4.0 * MD_ETA));
-  z.r = ru_fma_ab(MD_U, z.re, ru_fma_ab(MD_U, z.im, ru_fma_ab(MD_U, p1, ru_fma_ab(MD_U, p2, t))));
+  const double ma = ru_add_aa(a.re, dabs(a.im));  // |a.re| + |a.im|
+  const double mb = ru_add_aa(b.re, dabs(b.im));  // |b.re| + |b.im|
+  const double t = ru_fma(2.0001 * MD_U, mb, b.r);
+  z.r = ru_fma(ma, t, ru_fma(a.r, ru_add(mb, b.r), 8.0 * MD_ETA));
   return z;
 }
 
