@@ -326,6 +326,16 @@ def measure_reach(binding, torch, arithmetic="rect"):
                 "refine_digits": True, "refined": s["refined"],
                 "status": binding.STATUS_NAMES[st], "max_radius": s["max_radius"]})
     plan.close()
+    # the refused random products once more with the re-run in discs (same length)
+    for n in (1 << 20, 1 << 21):
+        plan = binding.Plan(n, n, refine_disc=True)
+        a, b = pair(2, n)
+        st, res = plan.mul(a, b)
+        s = plan.stats()
+        out.append({"operand_bytes": n, "fft_length": 1 << s["log_n"], "operands": "random",
+                    "refine_disc": True, "refined": s["refined"],
+                    "status": binding.STATUS_NAMES[st], "max_radius": s["max_radius"]})
+        plan.close()
     return out
 
 

@@ -85,6 +85,12 @@ typedef struct {
                               (separate_transforms = 0; SSA_INVALID_ARGUMENT
                               otherwise) and launch shapes without the persistent
                               row pass.  Same products.                           */
+  int refine_disc;         /* 0 (default) or 1 with arithmetic = SSA_ARITH_RECT and the
+                              packed transform: ssa_mul re-runs a product whose
+                              rectangular enclosures hold several integers once more
+                              in FP64 discs (same digits, same length), before any
+                              base-16 refinement; stats.refined = 2 when that run
+                              produced it.  Batches report the first outcome.     */
 } ssa_plan_opts;
 
 typedef struct {
@@ -99,7 +105,8 @@ typedef struct {
                           result (SSA_FP32_FALLBACK plans only)                         */
   int fp32_attempt;    /* 1: the product went through an FP32 attempt                  */
   int refined;         /* 1: base 256 was too wide and the base-16 re-run produced it
-                          (plans with refine_digits)                                  */
+                          (plans with refine_digits); 2: the rectangles were too wide
+                          and the re-run in discs produced it (refine_disc)          */
 } ssa_stats;
 
 typedef struct ssa_plan ssa_plan;

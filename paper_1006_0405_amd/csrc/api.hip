@@ -273,6 +273,20 @@ ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b
       nb > p->max_nb)
     return SSA_INVALID_ARGUMENT;
   ssa_status r = run_once(p, a, na, b, nb, out, dbg, status, p->opts.digit_bits);
+  // refinement in discs: the same transform once more with circular enclosures
+  if (r == SSA_OK && *status == SSA_ENCLOSURE_TOO_WIDE && p->opts.refine_disc && !dbg) {
+    const int log_n = static_cast<int>(p->last.log_n);
+    const launch_cfg keep = p->cfg[log_n];
+    if (log_n > SMALL_MAX_LOG) {  // a disc launch shape: the plain row pass
+      p->cfg[log_n].disc = 1;
+      p->cfg[log_n].persist = 0;
+    }
+    p->opts.arithmetic = SSA_ARITH_DISC;
+    r = run_once(p, a, na, b, nb, out, dbg, status, p->opts.digit_bits);
+    p->opts.arithmetic = SSA_ARITH_RECT;
+    p->cfg[log_n] = keep;
+    p->last.refined = 2;
+  }
   // refinement: a base-256 product whose enclosures are too wide, again in base 16
   // (not for ssa_debug_enclosures: its buffer holds the base-256 transform only)
   if (r == SSA_OK && *status == SSA_ENCLOSURE_TOO_WIDE && p->opts.refine_digits && !dbg &&
@@ -304,7 +318,9 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
       (o.separate_transforms != 0 && o.separate_transforms != 1) ||
       (o.refine_digits != 0 && (o.refine_digits != 1 || o.digit_bits != 8)) ||
       (o.arithmetic != SSA_ARITH_RECT && o.arithmetic != SSA_ARITH_DISC) ||
-      (o.arithmetic == SSA_ARITH_DISC && o.separate_transforms != 0))
+      (o.arithmetic == SSA_ARITH_DISC && o.separate_transforms != 0) ||
+      (o.refine_disc != 0 && (o.refine_disc != 1 || o.arithmetic != SSA_ARITH_RECT ||
+                              o.separate_transforms != 0)))
     return SSA_INVALID_ARGUMENT;
   const uint64_t L = digits(max_na, o.digit_bits) + digits(max_nb, o.digit_bits) - 1;
   const int log_nmax = log_n_for(L);

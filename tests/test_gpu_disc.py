@@ -203,6 +203,35 @@ def test_disc_fp32_attempt_exact_and_fallback_counts(digit_bits):
         used["rect"].count(0), used["disc"].count(0), len(used["rect"])))
 
 
+def test_refine_disc_rescues_a_product_too_wide_in_rectangles():
+    """1 MiB random operands (N = 2^21): the rectangles hold several integers,
+    the re-run in discs certifies the exact product (stats.refined = 2)."""
+    n = 1 << 20
+    a, b = pair(2, n)
+    want = (int.from_bytes(a.tobytes(), "little") *
+            int.from_bytes(b.tobytes(), "little")).to_bytes(2 * n, "little")
+    plain = binding.Plan(n, n)
+    st, out = plain.mul(a, b)
+    assert st == binding.SSA_ENCLOSURE_TOO_WIDE
+    assert not _np(out).any()
+    plain.close()
+    plan = binding.Plan(n, n, refine_disc=True)
+    st, out = plan.mul(a, b)
+    s = plan.stats()
+    assert st == binding.SSA_OK and s["refined"] == 2
+    assert _np(out).tobytes() == want
+    print("1 MiB random: rectangles too wide, disc re-run radius %.4g" % s["max_radius"])
+    c, d = pair(3, 5000)  # certified at once: no re-run
+    st, out = plan.mul(c, d)
+    assert st == binding.SSA_OK and plan.stats()["refined"] == 0
+    assert np.array_equal(_np(out), int_product(c, d))
+    plan.close()
+    with pytest.raises(binding.SsaError):
+        binding.Plan(5000, 5000, arithmetic="disc", refine_disc=True)
+    with pytest.raises(binding.SsaError):
+        binding.Plan(5000, 5000, separate_transforms=True, refine_disc=True)
+
+
 def test_disc_rejected_with_separate_transforms():
     with pytest.raises(binding.SsaError):
         binding.Plan(5000, 5000, separate_transforms=True, arithmetic="disc")
