@@ -12,10 +12,13 @@
 // thread's registers, so input and output are both in natural order.
 //
 // Radix 8 needs two exchanges for M = 512 (radix 4 needs four), which halves
-// the LDS traffic per element.  An exchange moves each 32-byte interval in two
-// 16-byte halves (real bounds, then imaginary bounds), so the exchange buffer is
-// M x 16 bytes.  When the group is one wavefront (M/8 <= 64) the exchanges need
-// no workgroup barrier: LDS operations of one wavefront complete in order.
+// the LDS traffic per element.  An exchange moves each element in two 16-byte
+// words (a rectangle's real bounds, then its imaginary bounds; a disc's
+// midpoint, then its radius), so the exchange buffer is M x 16 bytes.  The
+// element type is a template parameter: rectangles (ci) and discs (md) provide
+// the same operation names (e_add, e_tw, e_word0, ...).  When the group is one
+// wavefront (M/8 <= 64) the exchanges need no workgroup barrier: LDS operations
+// of one wavefront complete in order.
 #pragma once
 #include "fft.hpp"
 
@@ -87,9 +90,6 @@ template <class E> __device__ __forceinline__ void radix8(E v[8], double c8, dou
 // lpad_size(M) slots.
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 3); }
 __host__ __device__ constexpr size_t lpad_size(size_t m) { return m + (m >> 3); }
-__device__ __forceinline__ void hput(double2 *h, int idx, double x, double y) {
-  h[idx] = make_double2(x, y);
-}
 
 // Move the 8 values of this thread to positions wpos(q) and read back the
 // values at rpos(r) = j + r M/8, in two 16-byte rounds.  Element i of the

@@ -129,7 +129,9 @@ __device__ __forceinline__ bool sign_clear(double a) {
 }
 
 // ---- Rectangular complex interval, lower bounds negated --------------------
-// re in [-rn, rh], im in [-in, ih].  32 bytes, the unit of every FFT array.
+// re in [-rn, rh], im in [-in, ih].  32 bytes in registers and in the
+// standalone transform's arrays; the product's arrays between passes keep a
+// midpoint and one radius instead (20 bytes).
 struct alignas(16) ci {
   double rn, rh, in, ih;
 };

@@ -20,7 +20,9 @@
 //                the 1/N scale, certification of both parts;
 //    k_carry   : carries as a generate/propagate scan with decoupled look-back.
 // The inverse DFT is computed as conj(DFT(conj(.)))/N, so a single forward
-// interval DFT serves every transform; conjugation is exact.
+// interval DFT serves every transform; conjugation is exact.  The packed-path
+// kernels take the element type as a template parameter: rectangles (ci, the
+// paper's section 2.5) or FP64 discs (md, its section 4 variant).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
