@@ -680,31 +680,64 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
 #pragma unroll
   for (int r = 0; r < 8; ++r) v[r] = mr_load<E>(mr_of(tk.ya, log_n), row + j + r * M8);
   fft8_group<LOG_N2, WAVE, true>(v, j, hown, 0, T);
-  // partner values, real halves then imaginary halves (workgroup barriers:
-  // the partner row may be another wavefront)
+  // Each pair {k, -k} of the two rows needs one product: C_{-k} = conj(C_k)
+  // (the coefficients are real).  Elements k2 < N2/2 (r < 4) compute it from
+  // their partner's value, and hand it to the partner, whose element lies in
+  // the other half (k2 >= N2/2) -- except in row 0, where k2 = N2/2 is its own
+  // partner and k2 = 0 is partnered with itself too.  Exchanges go in 16-byte
+  // words through LDS, with workgroup barriers (the partner row may be another
+  // wavefront).
   uint32_t src[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const uint32_t k2 = j + r * M8;
     src[r] = k1 == 0 ? ((N2 - k2) & (N2 - 1)) : (N2 - 1 - k2);
   }
-  double2 pr[8];
+  const bool own4 = k1 == 0 && j == 0;  // k2 = N2/2 of row 0: its own partner
+  // 1. partner values for r < 4 (and the self-partnered element)
+  double2 pr[5];
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 8; ++r) hown[lpad(j + r * M8)] = e_word0(v[r]);
+  for (int r = 0; r < 8; ++r)
+    if (r >= 4 || own4) hown[lpad(j + r * M8)] = e_word0(v[r]);
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 8; ++r) pr[r] = hpart[lpad(src[r])];
+  for (int r = 0; r < 4; ++r) pr[r] = hpart[lpad(src[r])];
+  if (own4) pr[4] = hpart[lpad(src[4])];
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 8; ++r) hown[lpad(j + r * M8)] = e_word1(v[r]);
+  for (int r = 0; r < 8; ++r)
+    if (r >= 4 || own4) hown[lpad(j + r * M8)] = e_word1(v[r]);
   __syncthreads();
+  E C[4];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
+  for (int r = 0; r < 4; ++r) {
     E Zm;  // Z_{-k}
     e_from_words(Zm, pr[r], hpart[lpad(src[r])]);
-    v[r] = e_conj(separated_product(v[r], e_conj(Zm)));
+    C[r] = separated_product(v[r], e_conj(Zm));
   }
+  if (own4) {
+    E Zm;
+    e_from_words(Zm, pr[4], hpart[lpad(src[4])]);
+    v[4] = e_conj(separated_product(v[4], e_conj(Zm)));
+  }
+  // 2. the products to the partners: element -k receives C_k = conj(C_{-k})
+  double2 t0[4];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) hpart[lpad(src[r])] = e_word0(C[r]);
+  __syncthreads();
+#pragma unroll
+  for (int r = 4; r < 8; ++r) t0[r - 4] = hown[lpad(j + r * M8)];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) hpart[lpad(src[r])] = e_word1(C[r]);
+  __syncthreads();
+#pragma unroll
+  for (int r = 4; r < 8; ++r)
+    if (r != 4 || !own4) e_from_words(v[r], t0[r - 4], hown[lpad(j + r * M8)]);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = e_conj(C[r]);
   __syncthreads();  // the partner has read this row's buffer
   half_inverse_row<LOG_N2, WAVE>(v, j, k1, log_n1, hown, T, T, mr_of(tk.ya, log_n));
 }
