@@ -305,24 +305,56 @@ __device__ __forceinline__ void small_body(const task &tk, int bits, int mode, i
     } else {
       fft8_group<LOG_N, WAVE>(va, j, h, 0, T);
     }
-    // partners Z_{-k}: first words, then second words
-    double2 pr[8];
+    // One product per pair {k, -k} (C_{-k} = conj C_k, the coefficients are
+    // real): k < N/2 (r < 4) computes it from Z_{-k} and hands it to element
+    // -k; k = 0 and k = N/2 (thread 0, r = 0 and 4) are their own partners.
+    // Exchanges in 16-byte words through LDS.
+    const bool own4 = j == 0;
+    uint32_t src[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) src[r] = (0u - static_cast<uint32_t>(j + r * M8)) & mask;
+    double2 pr[5];
     xsync<WAVE>();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) h[lpad(j + r * M8)] = e_word0(va[r]);
+    for (int r = 0; r < 8; ++r)
+      if (r >= 4 || own4) h[lpad(j + r * M8)] = e_word0(va[r]);
     xsync<WAVE>();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) pr[r] = h[lpad((0u - static_cast<uint32_t>(j + r * M8)) & mask)];
+    for (int r = 0; r < 4; ++r) pr[r] = h[lpad(src[r])];
+    if (own4) pr[4] = h[lpad(src[4])];
     xsync<WAVE>();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) h[lpad(j + r * M8)] = e_word1(va[r]);
+    for (int r = 0; r < 8; ++r)
+      if (r >= 4 || own4) h[lpad(j + r * M8)] = e_word1(va[r]);
     xsync<WAVE>();
+    E C[4];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
+    for (int r = 0; r < 4; ++r) {
       E Zm;  // Z_{-k}
-      e_from_words(Zm, pr[r], h[lpad((0u - static_cast<uint32_t>(j + r * M8)) & mask)]);
-      va[r] = e_conj(separated_product(va[r], e_conj(Zm)));
+      e_from_words(Zm, pr[r], h[lpad(src[r])]);
+      C[r] = separated_product(va[r], e_conj(Zm));
     }
+    if (own4) {
+      E Zm;
+      e_from_words(Zm, pr[4], h[lpad(src[4])]);
+      va[4] = e_conj(separated_product(va[4], e_conj(Zm)));
+    }
+    double2 t0[4];
+    xsync<WAVE>();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[lpad(src[r])] = e_word0(C[r]);
+    xsync<WAVE>();
+#pragma unroll
+    for (int r = 4; r < 8; ++r) t0[r - 4] = h[lpad(j + r * M8)];
+    xsync<WAVE>();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[lpad(src[r])] = e_word1(C[r]);
+    xsync<WAVE>();
+#pragma unroll
+    for (int r = 4; r < 8; ++r)
+      if (r != 4 || !own4) e_from_words(va[r], t0[r - 4], h[lpad(j + r * M8)]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) va[r] = e_conj(C[r]);
   } else {  // one transform per operand, pointwise product
     ci vb[8];
 #pragma unroll
