@@ -471,14 +471,18 @@ __global__ __launch_bounds__(512) void k_small(const task *tasks, int mode, int 
 // entries: the two factors come from 2^(log_n - h) and 2^h contiguous entries,
 // which stay cache-resident, instead of one scattered read over all N entries.
 // The product's error has one bound for every pair (pass_tw_bound).
-template <class E>
+// UH: the caller guarantees t < N/2.  Then the root lies in the upper half
+// plane and so does the computed point: its sine is either exactly 0 (t = 0)
+// or at least sin(2 pi/N) > 10^-6 for N <= 2^22, far above the product's
+// rounding, so the known-sign form of the rotation applies.
+template <bool UH = false, class E>
 __device__ __forceinline__ E apply_pass_tw(const E &v, const twtab &T, uint32_t a, uint32_t b,
                                            int log_n) {
   const uint32_t t = (a * b) & ((1u << log_n) - 1u);
   const int h = (log_n + 1) >> 1;
   // omega_N^t = omega_{N / 2^h}^{t >> h} * omega_N^{t mod 2^h}
   const double2 w = tw_point_product(root(T, log_n - h, t >> h), root(T, log_n, t & ((1u << h) - 1u)));
-  return e_tw(v, w.x, w.y, pass_tw_bound(T.e));
+  return UH ? e_tw_uh(v, w.x, w.y, pass_tw_bound(T.e)) : e_tw(v, w.x, w.y, pass_tw_bound(T.e));
 }
 
 
@@ -551,7 +555,7 @@ __device__ __forceinline__ void mr_store(const mrbuf &b, size_t idx, const md &v
 template <class E>
 __device__ __forceinline__ E half_inverse_input(const E &P, const E &Q, const twtab &T, uint32_t k,
                                                 int log_n) {
-  const E t = apply_pass_tw(e_sub(P, Q), T, k, 1u, log_n);
+  const E t = apply_pass_tw<true>(e_sub(P, Q), T, k, 1u, log_n);  // k < N/2
   return e_add(e_add(P, Q), e_mul_negi(t));
 }
 
