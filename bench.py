@@ -339,13 +339,13 @@ def measure_reach(binding, torch, arithmetic="rect"):
     return out
 
 
-def measure_disc(binding, torch, A, Bs, steps, warmup):
-    """The timed workload (the same operands) with the three passes in FP64
-    discs (plan option arithmetic="disc"): autotuned shape, products checked,
-    graph launches timed like the main line, per-kernel times from eager
-    launches with HIP events."""
+def measure_arith(binding, torch, A, Bs, steps, warmup, arithmetic):
+    """The timed workload (the same operands) in another arithmetic: FP64
+    discs ("disc") or the non-rigorous point baseline ("naive"); autotuned
+    shape, products checked, graph launches timed like the main line,
+    per-kernel times from eager launches with HIP events."""
     n = len(A[0])
-    plan = binding.Plan(n, n, arithmetic="disc")
+    plan = binding.Plan(n, n, arithmetic=arithmetic)
     log_n = binding.fft_size(n, n).bit_length() - 1
     tuned = plan.autotune(log_n, count=len(A))
     batch = binding.Batch(plan, A, Bs)
@@ -354,7 +354,7 @@ def measure_disc(binding, torch, A, Bs, steps, warmup):
     for i in range(len(A)):
         want = (int.from_bytes(A[i].tobytes(), "little") *
                 int.from_bytes(Bs[i].tobytes(), "little")).to_bytes(2 * n, "little")
-        assert batch.OUT[i].cpu().numpy().tobytes() == want, "disc product %d is wrong" % i
+        assert batch.OUT[i].cpu().numpy().tobytes() == want, "%s product %d is wrong" % (arithmetic, i)
     max_rad = max(s["max_radius"] for s in batch.stats())
     for _ in range(warmup):
         batch.run()
@@ -392,7 +392,7 @@ def main():
     ap.add_argument("--no-singles", action="store_true",
                     help="skip the one-at-a-time products (1,024, 75,000 and 1,000,000 bytes)")
     ap.add_argument("--no-disc", action="store_true",
-                    help="skip the same workload with the three passes in FP64 discs")
+                    help="skip the same workload in FP64 discs and in the naive point baseline")
     ap.add_argument("--no-fft", action="store_true",
                     help="skip the standalone forward interval FFT (64 transforms of 2^18)")
     ap.add_argument("--separate-transforms", action="store_true",
@@ -556,9 +556,15 @@ def main():
     batch.close()
     plan.close()
     if not args.no_disc:
-        d = measure_disc(binding, torch, A, Bs, args.steps, args.warmup)
+        d = measure_arith(binding, torch, A, Bs, args.steps, args.warmup, "disc")
         d["speedup_vs_rect"] = d["products_per_s"] / value
         result["disc_fp64_2p18"] = d
+        # the non-rigorous point baseline: what the rigour costs on this GPU
+        d = measure_arith(binding, torch, A, Bs, args.steps, args.warmup, "naive")
+        d["rect_cost_factor"] = d["products_per_s"] / value
+        d["note"] = "not rigorous: coefficients rounded without a certificate; max_radius " \
+                    "is the largest distance of a coefficient to its integer"
+        result["naive_fp64_2p18"] = d
 
     if not args.no_singles:
         result["single_products"] = measure_singles(binding, torch)

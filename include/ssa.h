@@ -48,7 +48,7 @@ typedef enum {
 } ssa_status;
 
 enum { SSA_FP64 = 0, SSA_FP32_FALLBACK = 1 };
-enum { SSA_ARITH_RECT = 0, SSA_ARITH_DISC = 1 };
+enum { SSA_ARITH_RECT = 0, SSA_ARITH_DISC = 1, SSA_ARITH_NAIVE = 2 };
 enum { SSA_CERTIFY_ONE_INTEGER = 0, SSA_CERTIFY_HALF_INTEGER = 1 };
 
 typedef struct {
@@ -84,7 +84,16 @@ typedef struct {
                               transform either way.  Needs the packed transform
                               (separate_transforms = 0; SSA_INVALID_ARGUMENT
                               otherwise) and launch shapes without the persistent
-                              row pass.  Same products.                           */
+                              row pass.  Same products.
+                              SSA_ARITH_NAIVE: NOT RIGOROUS, a baseline for the cost
+                              of the intervals: the same kernels on plain complex
+                              doubles rounded to nearest, each coefficient rounded to
+                              the nearest integer without a certificate; the product
+                              can be wrong and the status only says the run ended.
+                              stats.max_radius holds the largest distance of a
+                              coefficient to its integer.  Needs precision SSA_FP64,
+                              the packed transform, no refinement, and launch shapes
+                              without the persistent row pass.                    */
   int refine_disc;         /* 0 (default) or 1 with arithmetic = SSA_ARITH_RECT and the
                               packed transform: ssa_mul re-runs a product whose
                               rectangular enclosures hold several integers once more

@@ -27,8 +27,9 @@ STATUS_NAMES = {0: "OK", 1: "ENCLOSURE_TOO_WIDE", 2: "INVALID_ARGUMENT", 3: "OUT
 SSA_FP64 = 0
 SSA_FP32_FALLBACK = 1
 PRECISIONS = {"fp64": SSA_FP64, "fp32_fallback": SSA_FP32_FALLBACK}
-SSA_ARITH_RECT, SSA_ARITH_DISC = 0, 1
-ARITHMETICS = {"rect": SSA_ARITH_RECT, "disc": SSA_ARITH_DISC}
+SSA_ARITH_RECT, SSA_ARITH_DISC, SSA_ARITH_NAIVE = 0, 1, 2
+# "naive": the non-rigorous point-arithmetic baseline (products not certified)
+ARITHMETICS = {"rect": SSA_ARITH_RECT, "disc": SSA_ARITH_DISC, "naive": SSA_ARITH_NAIVE}
 SSA_CERTIFY_ONE_INTEGER = 0
 SSA_CERTIFY_HALF_INTEGER = 1
 

@@ -35,7 +35,11 @@ uint64_t digits(size_t n, int bits) { return bits == 4 ? 2 * uint64_t(n) : uint6
 // Default launch shape of the three-pass path for N = 2^log_n (8 elements per
 // thread): C adjacent columns per column-pass workgroup (256 threads, 512 for
 // N1 = 2^11), and G rows (or row pairs) per row-pass workgroup.
-launch_cfg default_cfg(int log_n, int pack, int disc) {
+static_assert(ARITH_RECT == SSA_ARITH_RECT && ARITH_DISC == SSA_ARITH_DISC &&
+                  ARITH_POINT == SSA_ARITH_NAIVE,
+              "the kernels' element types follow ssa_plan_opts.arithmetic");
+
+launch_cfg default_cfg(int log_n, int pack, int arith) {
   launch_cfg c;
   c.log_n1 = log_n / 2;
   c.log_n2 = log_n - c.log_n1;
@@ -44,7 +48,7 @@ launch_cfg default_cfg(int log_n, int pack, int disc) {
   c.pack = pack;
   c.persist = 0;
   c.icols = c.cols;
-  c.disc = disc;
+  c.arith = arith;
   const int t = N2 / 8;  // threads per row
   if (pack)
     c.rows = std::max(1, std::min(N1 / 2, 128 / t));
@@ -73,7 +77,8 @@ bool cfg_valid(const launch_cfg &c, int log_n) {
   if (rt > 512 || rt % 64) return false;
   if (static_cast<size_t>(per) * c.rows * (N2 + N2 / 8) * 16 > 81920) return false;
   if (c.persist != 0 && c.persist != 1) return false;
-  if (c.disc && (!c.pack || c.persist)) return false;  // discs: packed transform, plain row pass
+  // discs and points: packed transform, plain row pass
+  if (c.arith != ARITH_RECT && (!c.pack || c.persist)) return false;
   // the persistent row pass: packed rows of one wavefront, twiddle levels in LDS
   if (c.persist && (!c.pack || c.log_n2 > 9 ||
                     (2 * static_cast<size_t>(c.rows) * (N2 + N2 / 8) + (size_t(2) << c.log_n2)) * 16 > 81920))
@@ -214,15 +219,15 @@ hipError_t enqueue_class(const ssa_plan *p, const task *d_tasks, int n, int n32,
   if (bits == 0) bits = p->opts.digit_bits;
   const int mode = p->force_too_wide ? CERT_FORCE_TOO_WIDE : p->opts.certify_mode;
   const int pack = p->opts.separate_transforms ? 0 : 1;
-  const int disc = p->opts.arithmetic == SSA_ARITH_DISC ? 1 : 0;
+  const int arith = p->opts.arithmetic;
   if (log_n <= SMALL_MAX_LOG) {
     if (n32 == 0)
-      return launch_small(d_tasks, n, log_n, bits, mode, pack, disc, 0, 0, 0, tw_of(p), dbg, s, hk);
+      return launch_small(d_tasks, n, log_n, bits, mode, pack, arith, 0, 0, 0, tw_of(p), dbg, s, hk);
     // FP32 attempt, then FP64 over the class except what the attempt certified
-    const hipError_t e = launch_small(d_tasks, n32, log_n, bits, mode, pack, disc, 1, 0, p->hooks,
+    const hipError_t e = launch_small(d_tasks, n32, log_n, bits, mode, pack, arith, 1, 0, p->hooks,
                                       tw_of(p), dbg, s, hk);
     if (e != hipSuccess) return e;
-    return launch_small(d_tasks, n, log_n, bits, mode, pack, disc, 0, 1, 0, tw_of(p), dbg, s, hk);
+    return launch_small(d_tasks, n, log_n, bits, mode, pack, arith, 0, 1, 0, tw_of(p), dbg, s, hk);
   }
   return launch_multipass(d_tasks, n, log_n, p->cfg[log_n], bits, mode, tw_of(p), dbg, s, hk);
 }
@@ -278,7 +283,7 @@ ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b
     const int log_n = static_cast<int>(p->last.log_n);
     const launch_cfg keep = p->cfg[log_n];
     if (log_n > SMALL_MAX_LOG) {  // a disc launch shape: the plain row pass
-      p->cfg[log_n].disc = 1;
+      p->cfg[log_n].arith = ARITH_DISC;
       p->cfg[log_n].persist = 0;
     }
     p->opts.arithmetic = SSA_ARITH_DISC;
@@ -317,8 +322,10 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
       (o.precision != SSA_FP64 && o.precision != SSA_FP32_FALLBACK) ||
       (o.separate_transforms != 0 && o.separate_transforms != 1) ||
       (o.refine_digits != 0 && (o.refine_digits != 1 || o.digit_bits != 8)) ||
-      (o.arithmetic != SSA_ARITH_RECT && o.arithmetic != SSA_ARITH_DISC) ||
-      (o.arithmetic == SSA_ARITH_DISC && o.separate_transforms != 0) ||
+      (o.arithmetic != SSA_ARITH_RECT && o.arithmetic != SSA_ARITH_DISC &&
+       o.arithmetic != SSA_ARITH_NAIVE) ||
+      (o.arithmetic != SSA_ARITH_RECT && o.separate_transforms != 0) ||
+      (o.arithmetic == SSA_ARITH_NAIVE && (o.precision != SSA_FP64 || o.refine_digits != 0)) ||
       (o.refine_disc != 0 && (o.refine_disc != 1 || o.arithmetic != SSA_ARITH_RECT ||
                               o.separate_transforms != 0)))
     return SSA_INVALID_ARGUMENT;
@@ -345,7 +352,7 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
   p->log_nref = log_nref;
   p->log_ntab = log_nalloc;
   for (int l = SMALL_MAX_LOG + 1; l <= MAX_LOG_N; ++l)
-    p->cfg[l] = default_cfg(l, o.separate_transforms ? 0 : 1, o.arithmetic == SSA_ARITH_DISC ? 1 : 0);
+    p->cfg[l] = default_cfg(l, o.separate_transforms ? 0 : 1, o.arithmetic);
   const size_t N = size_t(1) << log_nalloc;
   const size_t ntiles = (max_na + max_nb + CARRY_TILE - 1) / CARRY_TILE;
   bool ok = hip_ok(hipMalloc(&p->tab, sizeof(double2) << (p->log_ntab + 1))) &&  // level tables
@@ -777,7 +784,7 @@ ssa_status ssa_mul_batch(ssa_plan *plan, size_t count, const uint8_t *const *a, 
 // ---------------------------------------------------------------------------
 // Launch shapes and the autotuner
 
-static launch_cfg from_public(const ssa_launch_config &c, int log_n, int pack, int disc) {
+static launch_cfg from_public(const ssa_launch_config &c, int log_n, int pack, int arith) {
   launch_cfg r;
   r.log_n1 = c.log_n1;
   r.log_n2 = log_n - c.log_n1;
@@ -786,7 +793,7 @@ static launch_cfg from_public(const ssa_launch_config &c, int log_n, int pack, i
   r.pack = pack;
   r.persist = c.persistent;
   r.icols = c.inv_cols ? c.inv_cols : c.cols;
-  r.disc = disc;
+  r.arith = arith;
   return r;
 }
 
@@ -800,7 +807,7 @@ ssa_status ssa_plan_get_config(const ssa_plan *plan, int log_n, ssa_launch_confi
 ssa_status ssa_plan_set_config(ssa_plan *plan, int log_n, const ssa_launch_config *cfg) {
   if (!plan || !cfg || log_n <= SMALL_MAX_LOG || log_n > MAX_LOG_N) return SSA_INVALID_ARGUMENT;
   const launch_cfg c = from_public(*cfg, log_n, plan->opts.separate_transforms ? 0 : 1,
-                                   plan->opts.arithmetic == SSA_ARITH_DISC ? 1 : 0);
+                                   plan->opts.arithmetic);
   if (!cfg_valid(c, log_n)) return SSA_INVALID_ARGUMENT;
   plan->cfg[log_n] = c;
   return SSA_OK;
@@ -813,7 +820,7 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
     return SSA_INVALID_ARGUMENT;
   const int bits = plan->opts.digit_bits;
   const int pack = plan->opts.separate_transforms ? 0 : 1;
-  const int disc = plan->opts.arithmetic == SSA_ARITH_DISC ? 1 : 0;
+  const int arith = plan->opts.arithmetic;
   // equal operands as long as the plan allows, at most 2^(log_n - 1) digits each;
   // their transform length must be exactly 2^log_n
   const size_t nbytes = std::min(std::min(plan->max_na, plan->max_nb),
@@ -890,7 +897,7 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
     for (int cols = 1; cols <= 32 && ok; cols *= 2)
       for (int rows = 1; rows <= 64 && ok; rows *= 2)
         for (int persist = 0; persist <= 1 && ok; ++persist) {
-          const launch_cfg c{l1, log_n - l1, cols, rows, pack, persist, cols, disc};
+          const launch_cfg c{l1, log_n - l1, cols, rows, pack, persist, cols, arith};
           if (cfg_valid(c, log_n)) time_shape(c);
         }
   for (int pass = 0; pass < 2 && ok; ++pass) {

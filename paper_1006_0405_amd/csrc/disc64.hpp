@@ -130,4 +130,37 @@ __device__ __forceinline__ double2 e_word0(const md &a) { return make_double2(a.
 __device__ __forceinline__ double2 e_word1(const md &a) { return make_double2(a.r, 0.0); }
 __device__ __forceinline__ void e_from_words(md &a, double2 w0, double2 w1) { a = md{w0.x, w0.y, w1.x}; }
 
+// ---- Point complex numbers (a non-rigorous baseline) ----------------------
+// The same transforms with plain double complex values, round to nearest (the
+// kernels of this type leave MODE at its default): the naive method whose
+// cost the interval arithmetic is compared against.  Nothing is certified.
+struct pt {
+  double re, im;
+};
+__device__ __forceinline__ pt e_add(const pt &a, const pt &b) { return pt{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ pt e_sub(const pt &a, const pt &b) { return pt{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ pt e_mul_i(const pt &a) { return pt{-a.im, a.re}; }
+__device__ __forceinline__ pt e_mul_negi(const pt &a) { return pt{a.im, -a.re}; }
+__device__ __forceinline__ pt e_conj(const pt &a) { return pt{a.re, -a.im}; }
+__device__ __forceinline__ pt e_scale(const pt &a, double p2) { return pt{a.re * p2, a.im * p2}; }
+__device__ __forceinline__ pt e_tw(const pt &a, double c, double s, double) {
+  return pt{c * a.re - s * a.im, s * a.re + c * a.im};
+}
+__device__ __forceinline__ pt e_tw_q1(const pt &a, double c, double s, double e) { return e_tw(a, c, s, e); }
+__device__ __forceinline__ pt e_tw_uh(const pt &a, double c, double s, double e) { return e_tw(a, c, s, e); }
+__device__ __forceinline__ double2 e_word0(const pt &a) { return make_double2(a.re, a.im); }
+__device__ __forceinline__ double2 e_word1(const pt &) { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ void e_from_words(pt &a, double2 w0, double2) { a = pt{w0.x, w0.y}; }
+
+// Per element type: whether it is an enclosure (rigorous) and how many 16-byte
+// words an LDS exchange moves.
+template <class E> struct e_traits {
+  static constexpr bool rigorous = true;
+  static constexpr int words = 2;
+};
+template <> struct e_traits<pt> {
+  static constexpr bool rigorous = false;
+  static constexpr int words = 1;
+};
+
 }  // namespace ssa

@@ -64,6 +64,8 @@ __device__ __forceinline__ ci e_mul_w8(const ci &z, double c8, double e8) { retu
 __device__ __forceinline__ ci e_mul_w83(const ci &z, double c8, double e8) { return ci_mul_w83(z, c8, e8); }
 __device__ __forceinline__ md e_mul_w8(const md &z, double c8, double e8) { return md_tw(z, c8, c8, e8); }
 __device__ __forceinline__ md e_mul_w83(const md &z, double c8, double e8) { return md_tw(z, -c8, c8, e8); }
+__device__ __forceinline__ pt e_mul_w8(const pt &z, double c8, double e8) { return e_tw(z, c8, c8, e8); }
+__device__ __forceinline__ pt e_mul_w83(const pt &z, double c8, double e8) { return e_tw(z, -c8, c8, e8); }
 
 template <class E> __device__ __forceinline__ void radix8(E v[8], double c8, double e8) {
   E a[4], b[4];
@@ -103,6 +105,11 @@ __device__ __forceinline__ void exchange8(E v[8], int j, int M8, double2 *h, int
   xsync<WAVE>();
 #pragma unroll
   for (int r = 0; r < 8; ++r) t[r] = h[lpad(j + r * M8) << lis];
+  if constexpr (e_traits<E>::words == 1) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) e_from_words(v[r], t[r], t[r]);
+    return;
+  }
   xsync<WAVE>();
 #pragma unroll
   for (int q = 0; q < 8; ++q) h[lpad(wpos(q)) << lis] = e_word1(v[q]);
@@ -197,6 +204,11 @@ __device__ __forceinline__ void exchange4(E v[4], int j, int M4, double2 *h, W w
   xsync<WAVE>();
 #pragma unroll
   for (int r = 0; r < 4; ++r) t[r] = h[lpad(j + r * M4)];
+  if constexpr (e_traits<E>::words == 1) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) e_from_words(v[r], t[r], t[r]);
+    return;
+  }
   xsync<WAVE>();
 #pragma unroll
   for (int q = 0; q < 4; ++q) h[lpad(wpos(q))] = e_word1(v[q]);

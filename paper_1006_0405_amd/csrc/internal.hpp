@@ -39,6 +39,9 @@ struct task {
   uint32_t fp32;          // 1: FP32 first attempt, FP64 re-run on failure
 };
 
+// Element types of the transforms (the values of ssa_plan_opts.arithmetic).
+enum { ARITH_RECT = 0, ARITH_DISC = 1, ARITH_POINT = 2 };
+
 // CERT_FORCE_TOO_WIDE: test hook, every coefficient counts as too wide.
 enum { CERT_ONE_INTEGER = 0, CERT_HALF_INTEGER = 1, CERT_FORCE_TOO_WIDE = 2 };
 
@@ -63,7 +66,8 @@ struct launch_cfg {
   int pack;    // 1: one complex transform of a + i b; 0: one transform per operand
   int persist; // 1: persistent row-pair pass with next-item prefetch (pack, rows <= 2^9)
   int icols;   // columns per workgroup in the inverse column pass
-  int disc;    // 1: FP64 midpoint-radius discs instead of rectangles (packed, plain row pass)
+  int arith;   // element type: ARITH_RECT, ARITH_DISC or ARITH_POINT (the last two: packed,
+               // plain row pass)
 };
 
 struct twtab_host {
@@ -93,7 +97,7 @@ struct timing_hook {
 // fp32: FP32 first attempt over tasks that are all marked fp32; rerun: FP64
 // pass that follows it, skipping marked tasks that the attempt certified.
 hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bits, int cert_mode,
-                        int pack, int disc, int fp32, int rerun, int hooks, const twtab_host &tw,
+                        int pack, int arith, int fp32, int rerun, int hooks, const twtab_host &tw,
                         double *dbg, hipStream_t s, const timing_hook *hk = nullptr);
 hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const launch_cfg &cfg,
                             int digit_bits, int cert_mode, const twtab_host &tw, double *dbg,

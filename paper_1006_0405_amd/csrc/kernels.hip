@@ -246,15 +246,43 @@ __device__ __forceinline__ md separated_product(const md &Z, const md &W) {
   return md_mul(md{0.5 * S.re, 0.5 * S.im, 0.5 * S.r}, md{0.5 * D.im, -0.5 * D.re, 0.5 * D.r});
 }
 
+// FP64 rounding for an element type: toward +infinity for the enclosures, the
+// default (to nearest) for the point baseline.
+template <class E> __device__ __forceinline__ uint32_t enter_mode() {
+  if constexpr (e_traits<E>::rigorous) return enter_round_up();
+  return 0u;
+}
+
+// The point baseline's coefficient: the nearest integer, no certificate; the
+// distance to it is reported in place of a radius.
+__device__ __forceinline__ unsigned long long naive_round(double x, uint32_t i, uint32_t L,
+                                                          cert_acc &acc) {
+  if (i >= L) return 0ull;
+  const double m = __builtin_rint(x);
+  const double d = __builtin_fabs(x - m);
+  acc.rad = d > acc.rad ? d : acc.rad;
+  return m > 0.0 ? static_cast<unsigned long long>(m) : 0ull;
+}
+
+// The point baseline's pair separation: the same formula without enclosures.
+__device__ __forceinline__ pt separated_product(const pt &Z, const pt &W) {
+  const pt S = e_add(Z, W), D = e_sub(Z, W);
+  const pt A{0.5 * S.re, 0.5 * S.im}, B{0.5 * D.im, -0.5 * D.re};
+  return pt{A.re * B.re - A.im * B.im, A.re * B.im + A.im * B.re};
+}
+
 // A product's packed input element a + i b from two digits, thin.
 __device__ __forceinline__ void e_thin_pair(ci &z, double da, double db) { z = ci{-da, da, -db, db}; }
 __device__ __forceinline__ void e_thin_pair(md &z, double da, double db) { z = md{da, db, 0.0}; }
+__device__ __forceinline__ void e_thin_pair(pt &z, double da, double db) { z = pt{da, db}; }
 
 // Real-part and imaginary-part enclosures (negated lower bound, upper bound).
 __device__ __forceinline__ double2 e_re_nh(const ci &z) { return make_double2(z.rn, z.rh); }
 __device__ __forceinline__ double2 e_im_nh(const ci &z) { return make_double2(z.in, z.ih); }
 __device__ __forceinline__ double2 e_re_nh(const md &z) { return make_double2(md_re_n(z), md_re_h(z)); }
 __device__ __forceinline__ double2 e_im_nh(const md &z) { return make_double2(md_im_n(z), md_im_h(z)); }
+__device__ __forceinline__ double2 e_re_nh(const pt &z) { return make_double2(-z.re, z.re); }
+__device__ __forceinline__ double2 e_im_nh(const pt &z) { return make_double2(-z.im, z.im); }
 
 // ---------------------------------------------------------------------------
 // k_small: the whole product in one workgroup of N/8 threads, N = 2^log_n,
@@ -265,6 +293,9 @@ __device__ __forceinline__ double2 e_im_nh(const md &z) { return make_double2(md
 __device__ __forceinline__ void mr_to_e(const mr &a, ci &z) { z = mr_to_ci(a); }
 __device__ __forceinline__ void mr_to_e(const mr &a, md &z) {
   z = md{static_cast<double>(a.re), static_cast<double>(a.im), static_cast<double>(a.r)};
+}
+__device__ __forceinline__ void mr_to_e(const mr &a, pt &z) {  // (no FP32 attempt with points)
+  z = pt{static_cast<double>(a.re), static_cast<double>(a.im)};
 }
 
 // E: rectangles (ci), or discs (md) for the packed transform.
@@ -395,8 +426,12 @@ __device__ __forceinline__ void small_body(const task &tk, int bits, int mode, i
     const E v = e_scale(e_conj(va[r]), scale);
     const double2 re = e_re_nh(v), im = e_im_nh(v);
     if (dbg != nullptr && blockIdx.x == 0) dbg_store(dbg, i, ci{re.x, re.y, im.x, im.y});
-    // a real coefficient: the imaginary part must contain 0
-    cv[r] = certify_re(re.x, re.y, im.x >= 0.0 && im.y >= 0.0, i, tk.L, mode, acc);
+    if constexpr (e_traits<E>::rigorous) {
+      // a real coefficient: the imaginary part must contain 0
+      cv[r] = certify_re(re.x, re.y, im.x >= 0.0 && im.y >= 0.0, i, tk.L, mode, acc);
+    } else {
+      cv[r] = naive_round(re.y, i, tk.L, acc);
+    }
   }
   cert_reduce(sh, acc);
   __syncthreads();  // LDS free again; counters final
@@ -447,7 +482,7 @@ __global__ __launch_bounds__(512) void k_small(const task *tasks, int mode, int 
   extern __shared__ double2 hbuf[];
   __shared__ cert_shared sh;
   __shared__ uint32_t sh_waves[8];
-  const uint32_t z = enter_round_up();
+  const uint32_t z = enter_mode<E>();
   const task tk = after_mode(tasks, z)[blockIdx.x];
   T.tab = after_mode(T.tab, z);
   if (rerun && tk.fp32 != 0u && tk.st->too_wide == 0u && tk.st->internal == 0u) return;
@@ -542,6 +577,14 @@ __device__ __forceinline__ void mr_store(const mrbuf &b, size_t idx, const ci &v
 __device__ __forceinline__ void mr_store(const mrbuf &b, size_t idx, const md &v) {
   mr_put(b, idx, v.re, v.im, v.r);
 }
+// The point baseline keeps the midpoints only.
+template <> __device__ __forceinline__ pt mr_load<pt>(const mrbuf &b, size_t idx) {
+  const d2v m = gload(b.m + idx);
+  return pt{m.x, m.y};
+}
+__device__ __forceinline__ void mr_store(const mrbuf &b, size_t idx, const pt &v) {
+  gstore(b.m + idx, d2v{v.re, v.im});
+}
 
 // Half-length inverse of a spectrum Z whose inverse transform x is real (the
 // product's coefficients): y_m = x_{2m} + i x_{2m+1}, m < N/2, is the
@@ -616,7 +659,7 @@ __device__ __forceinline__ void reset_product_state(const task &tk) {
 template <int LOG_N1, int pack, int bits, class E>
 __global__ __launch_bounds__(512) void k_col_fwd(const task *tasks, int log_n2, int lc, twtab T) {
   extern __shared__ double2 hbuf[];
-  const uint32_t z = enter_round_up();
+  const uint32_t z = enter_mode<E>();
   const task tk = after_mode(tasks, z)[blockIdx.z];
   T.tab = after_mode(T.tab, z);
   const int log_n = LOG_N1 + log_n2;
@@ -783,7 +826,7 @@ template <int LOG_N2, class E>
 // to scratch for the longest rows), which measured faster than two waves.
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k_row_pair(const task *tasks, int log_n1, int G, twtab T) {
   extern __shared__ double2 hbuf[];
-  const uint32_t z = enter_round_up();
+  const uint32_t z = enter_mode<E>();
   const task tk = after_mode(tasks, z)[gridDim.y - 1 - blockIdx.y];  // last written first
   T.tab = after_mode(T.tab, z);
   row_pair_body<LOG_N2, (LOG_N2 <= 9), E>(tk, log_n1, G, T, hbuf);
@@ -894,7 +937,7 @@ __global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n2, 
                                                  twtab T, double *dbg) {
   extern __shared__ double2 hbuf[];
   __shared__ cert_shared sh;
-  const uint32_t z = enter_round_up();
+  const uint32_t z = enter_mode<E>();
   const task tk = after_mode(tasks, z)[blockIdx.y];
   T.tab = after_mode(T.tab, z);
   const int log_n = LOG_N1 + log_n2;
@@ -921,8 +964,14 @@ __global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n2, 
       dbg_store(dbg, i, ci{re.x, re.y, 0.0, 0.0});
       dbg_store(dbg, i + 1, ci{im.x, im.y, 0.0, 0.0});
     }
-    const unsigned long long c0 = certify_re(re.x, re.y, true, i, tk.L, mode, acc);
-    const unsigned long long c1 = certify_re(im.x, im.y, true, i + 1, tk.L, mode, acc);
+    unsigned long long c0, c1;
+    if constexpr (e_traits<E>::rigorous) {
+      c0 = certify_re(re.x, re.y, true, i, tk.L, mode, acc);
+      c1 = certify_re(im.x, im.y, true, i + 1, tk.L, mode, acc);
+    } else {
+      c0 = naive_round(re.y, i, tk.L, acc);
+      c1 = naive_round(im.y, i + 1, tk.L, acc);
+    }
     if (i + 1 < tk.L) {
       u64x2 pair;
       pair.x = c0;
@@ -1161,16 +1210,19 @@ hipError_t set_kernel_attributes() {
 #define SSA_K_SMALL(L)                                                                      \
   reinterpret_cast<const void *>(&k_small<L, 8, 1, ci>), reinterpret_cast<const void *>(&k_small<L, 4, 1, ci>), \
       reinterpret_cast<const void *>(&k_small<L, 8, 0, ci>), reinterpret_cast<const void *>(&k_small<L, 4, 0, ci>), \
-      reinterpret_cast<const void *>(&k_small<L, 8, 1, md>), reinterpret_cast<const void *>(&k_small<L, 4, 1, md>),
+      reinterpret_cast<const void *>(&k_small<L, 8, 1, md>), reinterpret_cast<const void *>(&k_small<L, 4, 1, md>), \
+      reinterpret_cast<const void *>(&k_small<L, 8, 1, pt>), reinterpret_cast<const void *>(&k_small<L, 4, 1, pt>),
       SSA_SMALL_LENGTHS(SSA_K_SMALL)
 #undef SSA_K_SMALL
 #define SSA_K_PASS(L)                                                                    \
   reinterpret_cast<const void *>(&k_col_fwd<L, 1, 8, ci>), reinterpret_cast<const void *>(&k_col_fwd<L, 1, 4, ci>), \
       reinterpret_cast<const void *>(&k_col_fwd<L, 0, 8, ci>), reinterpret_cast<const void *>(&k_col_fwd<L, 0, 4, ci>), \
       reinterpret_cast<const void *>(&k_col_fwd<L, 1, 8, md>), reinterpret_cast<const void *>(&k_col_fwd<L, 1, 4, md>), \
+      reinterpret_cast<const void *>(&k_col_fwd<L, 1, 8, pt>), reinterpret_cast<const void *>(&k_col_fwd<L, 1, 4, pt>), \
       reinterpret_cast<const void *>(&k_row<L>), \
       reinterpret_cast<const void *>(&k_row_pair<L, ci>), reinterpret_cast<const void *>(&k_col_inv<L, ci>), \
       reinterpret_cast<const void *>(&k_row_pair<L, md>), reinterpret_cast<const void *>(&k_col_inv<L, md>), \
+      reinterpret_cast<const void *>(&k_row_pair<L, pt>), reinterpret_cast<const void *>(&k_col_inv<L, pt>), \
       reinterpret_cast<const void *>(&k_fft_col<L>), reinterpret_cast<const void *>(&k_fft_row<L>),
       SSA_PASS_LENGTHS(SSA_K_PASS)
 #undef SSA_K_PASS
@@ -1198,20 +1250,27 @@ static inline void mark(const timing_hook *hk, int kind, int phase) {
 }
 
 hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bits, int cert_mode,
-                        int pack, int disc, int fp32, int rerun, int hooks, const twtab_host &tw,
+                        int pack, int arith, int fp32, int rerun, int hooks, const twtab_host &tw,
                         double *dbg, hipStream_t s, const timing_hook *hk) {
   const int threads = 1 << (log_n - 3);
   const size_t lds = sizeof(double2) * lpad_size(size_t(1) << log_n);
-  if (disc && !pack) return hipErrorInvalidValue;  // discs: packed transform only
+  if (arith != ARITH_RECT && !pack) return hipErrorInvalidValue;  // discs, points: packed only
+  if (arith == ARITH_POINT && fp32) return hipErrorInvalidValue;
   mark(hk, KIND_SMALL, 0);
   switch (log_n) {
 #define SSA_L(L)                                                                               \
   case L:                                                                                      \
-    if (disc && digit_bits == 8)                                                                \
+    if (arith == ARITH_DISC && digit_bits == 8)                                                 \
       hipLaunchKernelGGL((k_small<L, 8, 1, md>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
                          cert_mode, fp32, rerun, hooks, to_dev(tw), dbg);                       \
-    else if (disc)                                                                              \
+    else if (arith == ARITH_DISC)                                                               \
       hipLaunchKernelGGL((k_small<L, 4, 1, md>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
+                         cert_mode, fp32, rerun, hooks, to_dev(tw), dbg);                       \
+    else if (arith == ARITH_POINT && digit_bits == 8)                                           \
+      hipLaunchKernelGGL((k_small<L, 8, 1, pt>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
+                         cert_mode, fp32, rerun, hooks, to_dev(tw), dbg);                       \
+    else if (arith == ARITH_POINT)                                                              \
+      hipLaunchKernelGGL((k_small<L, 4, 1, pt>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
                          cert_mode, fp32, rerun, hooks, to_dev(tw), dbg);                       \
     else if (digit_bits == 8 && pack)                                                           \
       hipLaunchKernelGGL((k_small<L, 8, 1, ci>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
@@ -1275,7 +1334,8 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
   const int lc = log2_int(cfg.cols);
   const twtab T = to_dev(tw);
   if (l1 < 6 || l1 > 11 || l2 < 6 || l2 > 11 || (1 << lc) != cfg.cols) return hipErrorInvalidValue;
-  if (cfg.disc && (!cfg.pack || cfg.persist)) return hipErrorInvalidValue;  // discs: packed, plain row pass
+  if (cfg.arith != ARITH_RECT && (!cfg.pack || cfg.persist))
+    return hipErrorInvalidValue;  // discs and points: packed transform, plain row pass
   {
     const int threads = cfg.cols * static_cast<int>(N1 / 8);
     const size_t lds = sizeof(double2) * lpad_size(N1) * cfg.cols;
@@ -1284,10 +1344,14 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
     switch (l1) {
 #define SSA_L(L)                                                                                     \
   case L:                                                                                            \
-    if (cfg.disc && digit_bits == 8)                                                                 \
+    if (cfg.arith == ARITH_DISC && digit_bits == 8)                                                  \
       hipLaunchKernelGGL((k_col_fwd<L, 1, 8, md>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
-    else if (cfg.disc)                                                                               \
+    else if (cfg.arith == ARITH_DISC)                                                                \
       hipLaunchKernelGGL((k_col_fwd<L, 1, 4, md>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
+    else if (cfg.arith == ARITH_POINT && digit_bits == 8)                                            \
+      hipLaunchKernelGGL((k_col_fwd<L, 1, 8, pt>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
+    else if (cfg.arith == ARITH_POINT)                                                               \
+      hipLaunchKernelGGL((k_col_fwd<L, 1, 4, pt>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
     else if (cfg.pack && digit_bits == 8)                                                            \
       hipLaunchKernelGGL((k_col_fwd<L, 1, 8, ci>), grid, dim3(threads), lds, s, d_tasks, l2, lc, T);  \
     else if (cfg.pack)                                                                               \
@@ -1334,8 +1398,10 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
     switch (l2) {
 #define SSA_L(L)                                                                                    \
   case L:                                                                                           \
-    if (cfg.disc)                                                                                   \
+    if (cfg.arith == ARITH_DISC)                                                                    \
       hipLaunchKernelGGL((k_row_pair<L, md>), grid, dim3(threads), lds, s, d_tasks, l1, cfg.rows, T); \
+    else if (cfg.arith == ARITH_POINT)                                                              \
+      hipLaunchKernelGGL((k_row_pair<L, pt>), grid, dim3(threads), lds, s, d_tasks, l1, cfg.rows, T); \
     else                                                                                            \
       hipLaunchKernelGGL((k_row_pair<L, ci>), grid, dim3(threads), lds, s, d_tasks, l1, cfg.rows, T); \
     break;
@@ -1372,8 +1438,11 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
     switch (l1) {
 #define SSA_L(L)                                                                                \
   case L:                                                                                       \
-    if (cfg.disc)                                                                               \
+    if (cfg.arith == ARITH_DISC)                                                                \
       hipLaunchKernelGGL((k_col_inv<L, md>), grid, dim3(threads), lds, s, d_tasks, l2, lci,    \
+                         cert_mode, T, dbg);                                                    \
+    else if (cfg.arith == ARITH_POINT)                                                          \
+      hipLaunchKernelGGL((k_col_inv<L, pt>), grid, dim3(threads), lds, s, d_tasks, l2, lci,    \
                          cert_mode, T, dbg);                                                    \
     else                                                                                        \
       hipLaunchKernelGGL((k_col_inv<L, ci>), grid, dim3(threads), lds, s, d_tasks, l2, lci,    \
