@@ -877,7 +877,7 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
     plan->cfg[log_n] = c;
     ok = hip_ok(enqueue_batch(bt, s, nullptr));  // warm-up
     if (!ok) return;
-    const int reps = 3;
+    const int reps = 8;  // shapes often differ by a few percent: average out the noise
     ok = hip_ok(hipEventRecord(e0, s));
     for (int k = 0; k < reps && ok; ++k) ok = hip_ok(enqueue_batch(bt, s, nullptr));
     ok = ok && hip_ok(hipEventRecord(e1, s)) && hip_ok(hipEventSynchronize(e1));
