@@ -410,8 +410,8 @@ def main():
                          "same kernels, so leave it off when profiling per-kernel averages)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the path has no multi-GPU component in this "
-              "build (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
