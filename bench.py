@@ -141,7 +141,7 @@ def fp64_rate(kinds, ms_per_launch):
 
 
 def measure_batch(binding, torch, digit_bits, steps, precision="fp64", A=None, B=None,
-                  arithmetic="rect"):
+                  arithmetic="rect", fp64_digit_bits=0):
     """Default: the 4096-product batch, operand lengths log-uniform in
     [64, 16384] bytes (seed 3).  One graph launch per step; every product
     checked once against CPython integers outside the timed region."""
@@ -149,7 +149,7 @@ def measure_batch(binding, torch, digit_bits, steps, precision="fp64", A=None, B
     if A is None:
         A, B = make_batch(seed=3)
     plan = binding.Plan(max(len(a) for a in A), max(len(b) for b in B), digit_bits=digit_bits,
-                        precision=precision, arithmetic=arithmetic)
+                        precision=precision, arithmetic=arithmetic, fp64_digit_bits=fp64_digit_bits)
     lengths = sorted({binding.fft_size(len(a), len(b), digit_bits).bit_length() - 1
                       for a, b in zip(A, B)})
     for lg in lengths:
@@ -182,6 +182,8 @@ def measure_batch(binding, torch, digit_bits, steps, precision="fp64", A=None, B
         "precision": precision,
         "arithmetic": arithmetic,
     }
+    if fp64_digit_bits:
+        res["fp64_digit_bits"] = fp64_digit_bits
     if precision != "fp64":
         n_try = sum(1 for s in stats if s["fp32_attempt"])
         n_fb = sum(1 for s in stats if s["fallback"])
@@ -587,6 +589,14 @@ def main():
                 rd = measure_batch(binding, torch, bits, steps, arithmetic="disc")
                 rd["speedup_vs_rect"] = rd["products_per_s"] / r64["products_per_s"]
                 result["batch_fp64_disc_" + base] = rd
+        # base 16 with the FP32 attempt, and the products the attempt is not given
+        # run in FP64 with base-256 digits; speedups over the base-256 FP64 batch
+        c3 = result["batch_fp64_base256"]["products_per_s"]
+        result["batch_fp32_fallback_base16"]["speedup_vs_fp64_base256"] = (
+            result["batch_fp32_fallback_base16"]["products_per_s"] / c3)
+        rr = measure_batch(binding, torch, 4, steps, precision="fp32_fallback", fp64_digit_bits=8)
+        rr["speedup_vs_fp64_base256"] = rr["products_per_s"] / c3
+        result["batch_fp32_fallback_base16_fp64_base256"] = rr
         # inside the FP32 frontier: 8192 products of 100 x 100 bytes, base 16
         # (L = 399, N = 512), where every FP32 attempt is expected to certify
         from paper_1006_0405_amd.workloads import pair

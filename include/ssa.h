@@ -100,6 +100,15 @@ typedef struct {
                               in FP64 discs (same digits, same length), before any
                               base-16 refinement; stats.refined = 2 when that run
                               produced it.  Batches report the first outcome.     */
+  int fp64_digit_bits;     /* 0 (default): every product uses digit_bits.  8, with
+                              precision SSA_FP32_FALLBACK and digit_bits = 4: a
+                              product that the length predictor does not give to the
+                              FP32 attempt goes straight to the FP64 path with base-256
+                              digits (a transform half as long as base 16 needs);
+                              the FP32 attempt and its re-runs keep base 16.  ssa_mul
+                              re-runs a base-256 product refused as too wide with
+                              base-16 digits (stats.refined = 1); batches report the
+                              base-256 outcome.  Same products.                    */
 } ssa_plan_opts;
 
 typedef struct {

@@ -51,7 +51,7 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("digit_bits", ctypes.c_int),
                 ("certify_mode", ctypes.c_int), ("separate_transforms", ctypes.c_int),
                 ("refine_digits", ctypes.c_int), ("arithmetic", ctypes.c_int),
-                ("refine_disc", ctypes.c_int)]
+                ("refine_disc", ctypes.c_int), ("fp64_digit_bits", ctypes.c_int)]
 
 
 class LaunchConfig(ctypes.Structure):
@@ -169,7 +169,7 @@ class Plan:
 
     def __init__(self, max_na, max_nb, digit_bits=8, certify_mode=SSA_CERTIFY_ONE_INTEGER,
                  separate_transforms=False, precision="fp64", stream=None, device=None,
-                 refine_digits=False, arithmetic="rect", refine_disc=False):
+                 refine_digits=False, arithmetic="rect", refine_disc=False, fp64_digit_bits=0):
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.digit_bits = digit_bits
@@ -182,7 +182,7 @@ class Plan:
         self.arithmetic = arithmetic
         opts = PlanOpts(PRECISIONS[precision], digit_bits, certify_mode,
                         int(bool(separate_transforms)), int(bool(refine_digits)),
-                        ARITHMETICS[arithmetic], int(bool(refine_disc)))
+                        ARITHMETICS[arithmetic], int(bool(refine_disc)), int(fp64_digit_bits))
         h = _vp()
         with torch.cuda.device(self.device):
             _check(lib().ssa_plan_create(ctypes.byref(h), max_na, max_nb, ctypes.byref(opts),

@@ -166,6 +166,7 @@ struct ssa_batch {
   std::vector<int> order;  // task slot -> caller index
   task *d_tasks = nullptr;
   std::vector<task> h_tasks;
+  std::vector<int> bits;  // digit size by task slot
   ci *arena = nullptr;
   unsigned long long *carena = nullptr;
   dev_stats *stats = nullptr;
@@ -209,6 +210,15 @@ twtab_host tw_of(const ssa_plan *p) { return twtab_host{p->tab, p->log_ntab, p->
 bool fp32_first(const ssa_plan *p, uint64_t L, int log_n) {
   return p->opts.precision == SSA_FP32_FALLBACK && log_n <= SMALL_MAX_LOG &&
          L <= p->fp32_max_L && p->e < 0x1p-47;
+}
+
+// Digit size of a product's first run: the plan's, unless the plan sends the
+// products that the FP32 attempt is not given to FP64 with other digits.
+int route_bits(const ssa_plan *p, size_t na, size_t nb) {
+  const int bits = p->opts.digit_bits;
+  if (p->opts.fp64_digit_bits == 0) return bits;
+  const uint64_t L = digits(na, bits) + digits(nb, bits) - 1;
+  return fp32_first(p, L, log_n_for(L)) ? bits : p->opts.fp64_digit_bits;
 }
 
 // Enqueue one product class: all tasks [d_tasks, d_tasks + n) share log_n, and
@@ -277,7 +287,8 @@ ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b
   if (!p || !a || !b || !out || !status || na == 0 || nb == 0 || na > p->max_na ||
       nb > p->max_nb)
     return SSA_INVALID_ARGUMENT;
-  ssa_status r = run_once(p, a, na, b, nb, out, dbg, status, p->opts.digit_bits);
+  const int bits0 = dbg ? p->opts.digit_bits : route_bits(p, na, nb);
+  ssa_status r = run_once(p, a, na, b, nb, out, dbg, status, bits0);
   // refinement in discs: the same transform once more with circular enclosures
   if (r == SSA_OK && *status == SSA_ENCLOSURE_TOO_WIDE && p->opts.refine_disc && !dbg) {
     const int log_n = static_cast<int>(p->last.log_n);
@@ -287,7 +298,7 @@ ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b
       p->cfg[log_n].persist = 0;
     }
     p->opts.arithmetic = SSA_ARITH_DISC;
-    r = run_once(p, a, na, b, nb, out, dbg, status, p->opts.digit_bits);
+    r = run_once(p, a, na, b, nb, out, dbg, status, bits0);
     p->opts.arithmetic = SSA_ARITH_RECT;
     p->cfg[log_n] = keep;
     p->last.refined = 2;
@@ -297,6 +308,11 @@ ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b
   if (r == SSA_OK && *status == SSA_ENCLOSURE_TOO_WIDE && p->opts.refine_digits && !dbg &&
       log_n_for(digits(na, 4) + digits(nb, 4) - 1) <= p->log_nref) {
     r = run_once(p, a, na, b, nb, out, dbg, status, 4);
+    p->last.refined = 1;
+  }
+  // a base-256 first run of a base-16 plan (fp64_digit_bits): again in the plan's digits
+  if (r == SSA_OK && *status == SSA_ENCLOSURE_TOO_WIDE && bits0 != p->opts.digit_bits) {
+    r = run_once(p, a, na, b, nb, out, dbg, status, p->opts.digit_bits);
     p->last.refined = 1;
   }
   return r;
@@ -327,7 +343,9 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
       (o.arithmetic != SSA_ARITH_RECT && o.separate_transforms != 0) ||
       (o.arithmetic == SSA_ARITH_NAIVE && (o.precision != SSA_FP64 || o.refine_digits != 0)) ||
       (o.refine_disc != 0 && (o.refine_disc != 1 || o.arithmetic != SSA_ARITH_RECT ||
-                              o.separate_transforms != 0)))
+                              o.separate_transforms != 0)) ||
+      (o.fp64_digit_bits != 0 && (o.fp64_digit_bits != 8 || o.digit_bits != 4 ||
+                                  o.precision != SSA_FP32_FALLBACK)))
     return SSA_INVALID_ARGUMENT;
   const uint64_t L = digits(max_na, o.digit_bits) + digits(max_nb, o.digit_bits) - 1;
   const int log_nmax = log_n_for(L);
@@ -525,7 +543,6 @@ hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk,
                          hipStream_t side = nullptr, hipEvent_t fork = nullptr,
                          hipEvent_t join = nullptr) {
   const ssa_plan *p = bt->plan;
-  const int bits = p->opts.digit_bits;
   size_t s0 = 0;
   const size_t count = bt->count;
   const bool split = side != nullptr && bt->n_multi >= 2;
@@ -536,18 +553,19 @@ hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk,
   }
   while (s0 < count) {
     size_t s1 = s0;
-    const int l = static_cast<int>(bt->h_tasks[s0].log_n);
-    while (s1 < count && static_cast<int>(bt->h_tasks[s1].log_n) == l) ++s1;
+    const int l = static_cast<int>(bt->h_tasks[s0].log_n), cb = bt->bits[s0];
+    while (s1 < count && static_cast<int>(bt->h_tasks[s1].log_n) == l && bt->bits[s1] == cb) ++s1;
     const int n = static_cast<int>(s1 - s0);
     int n32 = 0;
     while (n32 < n && bt->h_tasks[s0 + n32].fp32) ++n32;  // marked tasks lead their class
     if (split && l > SMALL_MAX_LOG && n >= 2) {
       const int h = n / 2;
-      hipError_t e = enqueue_class(p, bt->d_tasks + s0, h, 0, l, nullptr, s, hk);
-      if (e == hipSuccess) e = enqueue_class(p, bt->d_tasks + s0 + h, n - h, 0, l, nullptr, side, hk);
+      hipError_t e = enqueue_class(p, bt->d_tasks + s0, h, 0, l, nullptr, s, hk, cb);
+      if (e == hipSuccess)
+        e = enqueue_class(p, bt->d_tasks + s0 + h, n - h, 0, l, nullptr, side, hk, cb);
       if (e != hipSuccess) return e;
     } else {
-      const hipError_t e = enqueue_class(p, bt->d_tasks + s0, n, n32, l, nullptr, s, hk);
+      const hipError_t e = enqueue_class(p, bt->d_tasks + s0, n, n32, l, nullptr, s, hk, cb);
       if (e != hipSuccess) return e;
     }
     s0 = s1;
@@ -558,7 +576,9 @@ hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk,
     if (e != hipSuccess) return e;
   }
   if (bt->n_multi) {
-    hipError_t e = launch_carry(bt->d_tasks, static_cast<int>(bt->n_multi), bt->max_tiles, bits, s, hk);
+    // one digit size for every multi-pass product (the FP32 attempt is single-workgroup)
+    hipError_t e = launch_carry(bt->d_tasks, static_cast<int>(bt->n_multi), bt->max_tiles,
+                                bt->bits[0], s, hk);
     if (e != hipSuccess) return e;
   }
   hipError_t e = launch_status(bt->d_tasks, static_cast<int>(count), bt->d_status_slot, s, hk);
@@ -592,27 +612,29 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
   *batch = nullptr;
   if (!plan || count == 0 || !a || !na || !b || !nb || !out || count > (1u << 24))
     return SSA_INVALID_ARGUMENT;
-  const int bits = plan->opts.digit_bits;
-  std::vector<int> lg(count);
+  std::vector<int> lg(count), bits(count);
   std::vector<char> f32(count);
   for (size_t i = 0; i < count; ++i) {
     if (!a[i] || !b[i] || !out[i] || na[i] == 0 || nb[i] == 0 || na[i] > plan->max_na ||
         nb[i] > plan->max_nb)
       return SSA_INVALID_ARGUMENT;
-    const uint64_t L = digits(na[i], bits) + digits(nb[i], bits) - 1;
+    bits[i] = route_bits(plan, na[i], nb[i]);
+    const uint64_t L = digits(na[i], bits[i]) + digits(nb[i], bits[i]) - 1;
     lg[i] = log_n_for(L);
-    f32[i] = fp32_first(plan, L, lg[i]) ? 1 : 0;
+    f32[i] = (bits[i] == plan->opts.digit_bits && fp32_first(plan, L, lg[i])) ? 1 : 0;
   }
   ssa_batch *bt = new (std::nothrow) ssa_batch();
   if (!bt) return SSA_OUT_OF_MEMORY;
   bt->plan = plan;
   bt->count = count;
-  // group by transform length, largest first; within a length, the products
-  // marked for the FP32 attempt first
+  // group by transform length, largest first, then by digit size; within a
+  // group, the products marked for the FP32 attempt first
   bt->order.resize(count);
   for (size_t i = 0; i < count; ++i) bt->order[i] = static_cast<int>(i);
   std::stable_sort(bt->order.begin(), bt->order.end(), [&](int x, int y) {
-    return lg[x] != lg[y] ? lg[x] > lg[y] : f32[x] > f32[y];
+    if (lg[x] != lg[y]) return lg[x] > lg[y];
+    if (bits[x] != bits[y]) return bits[x] > bits[y];
+    return f32[x] > f32[y];
   });
   // scratch sizes
   size_t arena_elems = 0, c_elems = 0, tiles = 0;
@@ -639,9 +661,11 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
     return SSA_OUT_OF_MEMORY;
   }
   bt->h_tasks.resize(count);
+  bt->bits.resize(count);
   size_t ao = 0, co = 0, to = 0;
   for (size_t s = 0; s < count; ++s) {
     const int i = bt->order[s];
+    bt->bits[s] = bits[i];
     task &t = bt->h_tasks[s];
     std::memset(&t, 0, sizeof(t));
     t.a = a[i];
@@ -649,8 +673,8 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
     t.out = out[i];
     t.na = static_cast<uint32_t>(na[i]);
     t.nb = static_cast<uint32_t>(nb[i]);
-    t.nda = static_cast<uint32_t>(digits(na[i], bits));
-    t.ndb = static_cast<uint32_t>(digits(nb[i], bits));
+    t.nda = static_cast<uint32_t>(digits(na[i], bits[i]));
+    t.ndb = static_cast<uint32_t>(digits(nb[i], bits[i]));
     t.L = t.nda + t.ndb - 1;
     t.log_n = static_cast<uint32_t>(lg[i]);
     t.fp32 = static_cast<uint32_t>(f32[i]);
@@ -681,6 +705,10 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
     if (bt->h_tasks[k].log_n > static_cast<uint32_t>(SMALL_MAX_LOG)) {
       bt->n_multi = k + 1;  // multi-pass classes come first
       bt->max_tiles = std::max(bt->max_tiles, bt->h_tasks[k].ntiles);
+      if (bt->bits[k] != bt->bits[0]) {  // the carry launch takes one digit size
+        ssa_batch_destroy(bt);
+        return SSA_INTERNAL_ERROR;
+      }
     }
   // Capture the launch sequence into one graph.
   hipStream_t cs = nullptr, side = nullptr;

@@ -182,3 +182,72 @@ def test_fp32_batch_forced_fallback_twice():
         assert all(s["fallback"] == 1 and s["fp32_attempt"] == 1 for s in bt.stats())
     bt.close()
     plan.close()
+
+
+def _log_n(na, nb, bits):
+    return binding.fft_size(na, nb, bits).bit_length() - 1
+
+
+def test_fp64_digit_bits_batch_base16_exact():
+    """The uneven-length batch with base-16 digits and fp64_digit_bits = 8: the
+    products the length predictor gives to the FP32 attempt keep base 16, every
+    other product runs in FP64 with base-256 digits (half the transform
+    length).  Every product exact on two graph replays."""
+    A, B = batch(seed=3)
+    plan = binding.Plan(16384, 16384, digit_bits=4, precision="fp32_fallback", fp64_digit_bits=8)
+    bt = binding.Batch(plan, A, B)
+    for rep in range(2):
+        status = _np(bt.run())
+        assert np.all(status == binding.SSA_OK)
+    for i in range(len(A)):
+        assert np.array_equal(_np(bt.OUT[i]), int_product(A[i], B[i])), i
+    st = bt.stats()
+    n_try = 0
+    for (a, b), s in zip(zip(A, B), st):
+        attempt = 2 * (len(a) + len(b)) - 1 <= 511
+        n_try += attempt
+        assert s["fp32_attempt"] == int(attempt)
+        assert s["log_n"] == _log_n(len(a), len(b), 4 if attempt else 8)
+    print("FP32 attempts (base 16): %d; FP64 with base-256 digits: %d" % (n_try, len(st) - n_try))
+    assert 0 < n_try < len(st)
+    bt.close()
+    plan.close()
+
+
+def test_fp64_digit_bits_single_products():
+    """ssa_mul on a base-16 FP32_FALLBACK plan with fp64_digit_bits = 8: a short
+    product takes the FP32 attempt in base 16, a longer one goes straight to
+    FP64 with base-256 digits; both exact."""
+    plan = binding.Plan(6000, 6000, digit_bits=4, precision="fp32_fallback", fp64_digit_bits=8)
+    for na, nb, attempt in ((100, 100, True), (5000, 6000, False), (300, 1, False)):
+        a, b = pair(na + 7 * nb, na, nb)
+        st, out = plan.mul(a, b)
+        s = plan.stats()
+        assert st == binding.SSA_OK, (na, nb)
+        assert np.array_equal(_np(out), int_product(a, b)), (na, nb)
+        assert s["fp32_attempt"] == int(attempt) and s["refined"] == 0
+        assert s["log_n"] == _log_n(na, nb, 4 if attempt else 8)
+    plan.close()
+
+
+def test_fp64_digit_bits_rerun_in_base16():
+    """A random 1 MiB product is too wide in FP64 with base-256 digits
+    (N = 2^21); on a base-16 plan with fp64_digit_bits = 8, ssa_mul re-runs it
+    with the plan's base-16 digits (N = 2^22) and returns the exact product."""
+    n = 1 << 20
+    a, b = pair(2, n)
+    plan = binding.Plan(n, n, digit_bits=4, precision="fp32_fallback", fp64_digit_bits=8)
+    st, out = plan.mul(a, b)
+    s = plan.stats()
+    print("re-run:", s)
+    assert st == binding.SSA_OK and s["refined"] == 1 and s["log_n"] == 22
+    assert np.array_equal(_np(out), int_product(a, b))
+    plan.close()
+
+
+def test_fp64_digit_bits_arguments():
+    for kw in (dict(digit_bits=8, precision="fp32_fallback"), dict(digit_bits=4, precision="fp64")):
+        with pytest.raises(binding.SsaError):
+            binding.Plan(100, 100, fp64_digit_bits=8, **kw)
+    with pytest.raises(binding.SsaError):
+        binding.Plan(100, 100, digit_bits=4, precision="fp32_fallback", fp64_digit_bits=4)
