@@ -49,3 +49,19 @@ def test_workloads_are_seeded_and_shaped():
     assert len(na) == 4096 and na.min() >= 64 and nb.max() <= 16384
     # log-uniform: about half the lengths below the geometric mean 1024
     assert 0.4 < np.mean(na < 1024) < 0.6
+
+
+def _struct_fields(name):
+    """Field names of `typedef struct { ... } name;` in the header, in order."""
+    text = open(os.path.join(ROOT, "include", "ssa.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    m = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", text)
+    assert m, name
+    return [re.findall(r"(\w+)\s*$", decl.strip())[0] for decl in m.group(1).split(";") if decl.strip()]
+
+
+def test_binding_structures_mirror_the_header():
+    # the ctypes structures are passed by pointer through the C ABI: same fields, same order
+    for cname, cls in (("ssa_plan_opts", binding.PlanOpts), ("ssa_launch_config", binding.LaunchConfig),
+                       ("ssa_stats", binding.Stats)):
+        assert [f[0] for f in cls._fields_] == _struct_fields(cname), cname
