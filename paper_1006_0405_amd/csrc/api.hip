@@ -189,17 +189,17 @@ namespace {
 
 void free_plan(ssa_plan *p) {
   if (!p) return;
-  hipFree(p->tab);
-  hipFree(p->ebits);
-  hipFree(p->roots);
-  hipFree(p->ya);
-  hipFree(p->yb);
-  hipFree(p->c);
-  hipFree(p->st);
-  hipFree(p->tiles);
-  hipFree(p->d_task);
-  if (p->h_task) hipHostFree(p->h_task);
-  if (p->h_stats) hipHostFree(p->h_stats);
+  (void)hipFree(p->tab);
+  (void)hipFree(p->ebits);
+  (void)hipFree(p->roots);
+  (void)hipFree(p->ya);
+  (void)hipFree(p->yb);
+  (void)hipFree(p->c);
+  (void)hipFree(p->st);
+  (void)hipFree(p->tiles);
+  (void)hipFree(p->d_task);
+  if (p->h_task) (void)hipHostFree(p->h_task);
+  if (p->h_stats) (void)hipHostFree(p->h_stats);
   delete p;
 }
 
@@ -361,7 +361,7 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
   ssa_plan *p = new (std::nothrow) ssa_plan();
   if (!p) return SSA_OUT_OF_MEMORY;
   p->stream = static_cast<hipStream_t>(stream);
-  hipGetDevice(&p->device);
+  (void)hipGetDevice(&p->device);
   p->opts = o;
   if (o.precision == SSA_FP32_FALLBACK) p->fp32_max_L = default_fp32_max_L(o.digit_bits);
   p->max_na = max_na;
@@ -387,7 +387,7 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
          (!o.separate_transforms || hip_ok(hipMalloc(&p->yb, sizeof(ci) * N)));
   if (!ok) {
     free_plan(p);
-    hipGetLastError();
+    (void)hipGetLastError();
     return SSA_OUT_OF_MEMORY;
   }
   // certified twiddles: the bound e is read back once and passed by value
@@ -408,7 +408,7 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
 
 void ssa_plan_destroy(ssa_plan *plan) {
   if (!plan) return;
-  hipStreamSynchronize(plan->stream);
+  (void)hipStreamSynchronize(plan->stream);
   free_plan(plan);
 }
 
@@ -438,7 +438,7 @@ ssa_status ssa_fft_forward(ssa_plan *plan, int log_n, size_t count, const double
     for (hipEvent_t &e : ev)
       if (!hip_ok(hipEventCreate(&e))) {
         for (hipEvent_t f : ev)
-          if (f) hipEventDestroy(f);
+          if (f) (void)hipEventDestroy(f);
         return SSA_DEVICE_ERROR;
       }
   }
@@ -453,7 +453,7 @@ ssa_status ssa_fft_forward(ssa_plan *plan, int log_n, size_t count, const double
     pass_ms_host[1] = m1;
   }
   for (hipEvent_t f : ev)
-    if (f) hipEventDestroy(f);
+    if (f) (void)hipEventDestroy(f);
   if (!ok) return SSA_DEVICE_ERROR;
   *log_n1_host = c.log_n1;
   return SSA_OK;
@@ -508,18 +508,18 @@ ssa_status ssa_probe_directed(int op, const double *a, const double *b, const do
 
 void ssa_batch_destroy(ssa_batch *bt) {
   if (!bt) return;
-  if (bt->plan) hipStreamSynchronize(bt->plan->stream);
-  for (hipEvent_t ev : bt->events) hipEventDestroy(ev);
-  if (bt->exec) hipGraphExecDestroy(bt->exec);
-  if (bt->graph) hipGraphDestroy(bt->graph);
-  hipFree(bt->d_tasks);
-  hipFree(bt->arena);
-  hipFree(bt->carena);
-  hipFree(bt->stats);
-  hipFree(bt->tiles);
-  hipFree(bt->d_status_slot);
-  hipFree(bt->d_status);
-  hipFree(bt->d_order);
+  if (bt->plan) (void)hipStreamSynchronize(bt->plan->stream);
+  for (hipEvent_t ev : bt->events) (void)hipEventDestroy(ev);
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  (void)hipFree(bt->d_tasks);
+  (void)hipFree(bt->arena);
+  (void)hipFree(bt->carena);
+  (void)hipFree(bt->stats);
+  (void)hipFree(bt->tiles);
+  (void)hipFree(bt->d_status_slot);
+  (void)hipFree(bt->d_status);
+  (void)hipFree(bt->d_order);
   delete bt;
 }
 
@@ -657,7 +657,7 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
          hip_ok(hipMalloc(&bt->tiles, sizeof(uint32_t) * TILE_WORD_STRIDE * std::max<size_t>(tiles, 1)));
   if (!ok) {
     ssa_batch_destroy(bt);
-    hipGetLastError();
+    (void)hipGetLastError();
     return SSA_OUT_OF_MEMORY;
   }
   bt->h_tasks.resize(count);
@@ -728,15 +728,15 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
     bt->graph = g;
     ok = hip_ok(hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0));
   } else if (g) {
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
   }
-  if (cs) hipStreamDestroy(cs);
-  if (side) hipStreamDestroy(side);
-  if (fork) hipEventDestroy(fork);
-  if (join) hipEventDestroy(join);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (side) (void)hipStreamDestroy(side);
+  if (fork) (void)hipEventDestroy(fork);
+  if (join) (void)hipEventDestroy(join);
   if (!ok) {
     ssa_batch_destroy(bt);
-    hipGetLastError();
+    (void)hipGetLastError();
     return SSA_DEVICE_ERROR;
   }
   *batch = bt;
@@ -858,8 +858,8 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
   uint8_t *dops = nullptr, *dout = nullptr;
   const size_t ops_bytes = 2 * nbytes * count, out_bytes = 2 * nbytes * count;
   if (!hip_ok(hipMalloc(&dops, ops_bytes)) || !hip_ok(hipMalloc(&dout, out_bytes))) {
-    hipFree(dops);
-    hipGetLastError();
+    (void)hipFree(dops);
+    (void)hipGetLastError();
     return SSA_OUT_OF_MEMORY;
   }
   {  // pseudo-random operand bytes (xorshift), any content serves for timing
@@ -872,8 +872,8 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
       b = static_cast<uint8_t>(x >> 24);
     }
     if (!hip_ok(hipMemcpy(dops, h.data(), ops_bytes, hipMemcpyHostToDevice))) {
-      hipFree(dops);
-      hipFree(dout);
+      (void)hipFree(dops);
+      (void)hipFree(dout);
       return SSA_DEVICE_ERROR;
     }
   }
@@ -889,13 +889,13 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
   ssa_status r = ssa_batch_create(plan, count, pa.data(), na.data(), pb.data(), nb.data(),
                                   po.data(), &bt);
   if (r != SSA_OK) {
-    hipFree(dops);
-    hipFree(dout);
+    (void)hipFree(dops);
+    (void)hipFree(dout);
     return r;
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
   const launch_cfg keep = plan->cfg[log_n];
   launch_cfg bestc = keep;
   double bestms = 1e30;
@@ -937,13 +937,13 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
     }
   }
   plan->cfg[log_n] = ok ? bestc : keep;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   ssa_batch_destroy(bt);
-  hipFree(dops);
-  hipFree(dout);
+  (void)hipFree(dops);
+  (void)hipFree(dout);
   if (!ok) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return SSA_DEVICE_ERROR;
   }
   *best = ssa_launch_config{bestc.log_n1, bestc.cols, bestc.rows, bestc.persist, bestc.icols};

@@ -1311,7 +1311,7 @@ static uint32_t resident_workgroups(const void *kernel, int threads, size_t lds)
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess ||
       hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     per_cu = 1;
     cus = 1;
   }
@@ -1467,7 +1467,7 @@ hipError_t launch_fft_forward(const double *x, double *y, int count, const launc
   const twtab T = to_dev(tw);
   if (l1 < 6 || l1 > 11 || l2 < 6 || l2 > 11 || (1 << lc) != cfg.cols || count < 1 || count > 65535)
     return hipErrorInvalidValue;
-  if (ev) hipEventRecord(ev[0], s);
+  if (ev) (void)hipEventRecord(ev[0], s);
   {
     const int threads = cfg.cols * static_cast<int>(N1 / 8);
     const size_t lds = sizeof(double2) * lpad_size(N1) * cfg.cols;
@@ -1483,7 +1483,7 @@ hipError_t launch_fft_forward(const double *x, double *y, int count, const launc
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (ev) hipEventRecord(ev[1], s);
+  if (ev) (void)hipEventRecord(ev[1], s);
   {
     const int threads = cfg.rows * static_cast<int>(N2 / 8);
     const size_t lds = sizeof(double2) * lpad_size(N2) * cfg.rows;
@@ -1499,7 +1499,7 @@ hipError_t launch_fft_forward(const double *x, double *y, int count, const launc
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (ev) hipEventRecord(ev[2], s);
+  if (ev) (void)hipEventRecord(ev[2], s);
   return hipSuccess;
 }
 
