@@ -294,6 +294,47 @@ def measure_singles(binding, torch, reps=10):
     return out
 
 
+def measure_per_n(binding, torch, log_ns=range(10, 21), elements=1 << 23, steps=3):
+    """Throughput per transform length: for N = 2^k, a batch of products of two
+    uniform random 2^(k-1)-byte operands (L = 2^k - 1, so exactly this N),
+    max(4, 2^23 / N) products per launch, launch shape autotuned for k > 12.
+    Reports products/s and ns per transform element (the time per product over
+    N, which grows like log N between lengths and steps at the launch-shape
+    changes).  The first and last product of every batch are checked against
+    CPython's integers; products refused as too wide are counted, not timed
+    as certified."""
+    from paper_1006_0405_amd.workloads import pair
+    out = {}
+    for k in log_ns:
+        n = 1 << (k - 1)
+        count = max(4, elements >> k)
+        A, B = zip(*[pair(9_000 + 97 * k + i, n) for i in range(count)])
+        plan = binding.Plan(n, n)
+        if k > 12:
+            plan.autotune(k, count=min(count, 32))
+        bt = binding.Batch(plan, list(A), list(B))
+        status = bt.run().cpu().numpy()
+        for i in (0, count - 1):
+            if status[i] == binding.SSA_OK:
+                want = (int.from_bytes(A[i].tobytes(), "little") *
+                        int.from_bytes(B[i].tobytes(), "little")).to_bytes(2 * n, "little")
+                assert bt.OUT[i].cpu().numpy().tobytes() == want, (k, i)
+        bt.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            bt.run()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        cert = int(np.sum(bt.status.cpu().numpy() == binding.SSA_OK))
+        out[str(1 << k)] = {"operand_bytes": n, "products": count, "certified": cert,
+                            "products_per_s": cert / el, "ms_per_batch": el * 1e3,
+                            "ns_per_element": el * 1e9 / (count << k)}
+        bt.close()
+        plan.close()
+    return out
+
+
 def measure_reach(binding, torch, arithmetic="rect"):
     """How far the FP64 path (rectangles, or discs with arithmetic="disc")
     certifies base-256 products of two equal-length operands (uniform random
@@ -576,6 +617,9 @@ def main():
 
     if not args.no_fft:
         result["fft_forward_2p18"] = measure_fft(binding, torch, max(5, args.steps // 5))
+
+    if not args.no_batch:
+        result["per_fft_length_base256"] = measure_per_n(binding, torch)
 
     if not args.no_batch:
         steps = max(3, args.steps // 10)
