@@ -123,7 +123,8 @@ typedef struct {
                           result (SSA_FP32_FALLBACK plans only)                         */
   int fp32_attempt;    /* 1: the product went through an FP32 attempt                  */
   int refined;         /* 1: base 256 was too wide and the base-16 re-run produced it
-                          (plans with refine_digits); 2: the rectangles were too wide
+                          (plans with refine_digits or fp64_digit_bits); 2: the
+                          rectangles were too wide
                           and the re-run in discs produced it (refine_disc)          */
 } ssa_stats;
 
