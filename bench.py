@@ -69,7 +69,7 @@ def _cpu_worker(args):
         a, b = pair(seed, NBYTES)
     t0 = time.perf_counter()
     st, _, rad, _ = oracle.mul(a, b)
-    return st, time.perf_counter() - t0
+    return st, time.perf_counter() - t0, rad
 
 
 def cpu_baseline(nworkers):
@@ -82,8 +82,9 @@ def cpu_baseline(nworkers):
     with ctx.Pool(nworkers) as pool:
         res = pool.map(_cpu_worker, jobs)
     wall = time.perf_counter() - t0
-    ok = sum(1 for st, _ in res if st == 0)
-    cpu_s = sum(t for _, t in res)
+    ok = sum(1 for st, _, _ in res if st == 0)
+    cpu_s = sum(t for _, t, _ in res)
+    radii = [(kind, seed, rad) for (kind, seed), (_, _, rad) in zip(jobs, res)]
     return {
         "value": ok / wall,
         "unit": UNIT,
@@ -92,6 +93,9 @@ def cpu_baseline(nworkers):
         "sample": "%d products of 75,000 x 75,000 bytes (N = 2^18; half uniform random, half "
                   "all-0xFF), one per process, %.1f s of oracle CPU time over %.1f s wall; "
                   "%d certified" % (len(jobs), cpu_s, wall, ok),
+        # maximum real half-width of the oracle's enclosures per sampled product
+        "max_radius": {("all_ff" if kind == "ff" else "random_seed%d" % seed): rad
+                       for kind, seed, rad in radii},
     }
 
 
@@ -501,7 +505,12 @@ def main():
         want = (int.from_bytes(A[i].tobytes(), "little") *
                 int.from_bytes(Bs[i].tobytes(), "little")).to_bytes(2 * NBYTES, "little")
         assert got == want, "product %d is wrong" % i
-    max_rad = max(s["max_radius"] for s in batch.stats())
+    bstats = batch.stats()
+    max_rad = max(s["max_radius"] for s in bstats)
+    # per-product radii of the products the CPU baseline samples (same operands)
+    gpu_radius = {"all_ff": bstats[1]["max_radius"]} if B > 1 else {}
+    for i in range(0, B, 2):
+        gpu_radius["random_seed%d" % (2 + i // 2)] = bstats[i]["max_radius"]
 
     # the timed steps: one graph launch each (ssa_batch_run, the library's batch
     # entry point), bracketed by device synchronisation
@@ -654,6 +663,9 @@ def main():
     if not args.no_cpu_baseline:
         n = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
         result["cpu_baseline"] = cpu_baseline(n)
+        # maximum enclosure radius, this path beside the oracle, on the same products
+        result["radius_vs_oracle"] = {k: {"gpu": gpu_radius.get(k), "oracle": v}
+                                      for k, v in result["cpu_baseline"]["max_radius"].items()}
     else:
         result["cpu_baseline"] = None
     print(json.dumps(result), flush=True)
