@@ -178,6 +178,8 @@ struct ssa_batch {
   hipGraphExec_t exec = nullptr;
   uint32_t max_tiles = 0;
   size_t n_multi = 0;
+  uint2 *d_tile_map = nullptr;  // (task slot, tile) per carry workgroup
+  uint32_t total_tiles = 0;
   // timed (eager) runs: one event before and one after every kernel launch
   std::vector<hipEvent_t> events;
   std::vector<int> kinds;
@@ -517,6 +519,7 @@ void ssa_batch_destroy(ssa_batch *bt) {
   (void)hipFree(bt->carena);
   (void)hipFree(bt->stats);
   (void)hipFree(bt->tiles);
+  (void)hipFree(bt->d_tile_map);
   (void)hipFree(bt->d_status_slot);
   (void)hipFree(bt->d_status);
   (void)hipFree(bt->d_order);
@@ -577,8 +580,7 @@ hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk,
   }
   if (bt->n_multi) {
     // one digit size for every multi-pass product (the FP32 attempt is single-workgroup)
-    hipError_t e = launch_carry(bt->d_tasks, static_cast<int>(bt->n_multi), bt->max_tiles,
-                                bt->bits[0], s, hk);
+    hipError_t e = launch_carry_map(bt->d_tasks, bt->d_tile_map, bt->total_tiles, bt->bits[0], s, hk);
     if (e != hipSuccess) return e;
   }
   hipError_t e = launch_status(bt->d_tasks, static_cast<int>(count), bt->d_status_slot, s, hk);
@@ -710,6 +712,23 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
         return SSA_INTERNAL_ERROR;
       }
     }
+  // Carry workgroups: the multi-pass products' tiles, products in the reverse of
+  // their pass order (the last written is still in cache), tiles ascending.
+  if (bt->n_multi) {
+    std::vector<uint2> map;
+    for (size_t k = bt->n_multi; k-- > 0;)
+      for (uint32_t t = 0; t < bt->h_tasks[k].ntiles; ++t) map.push_back(make_uint2(static_cast<uint32_t>(k), t));
+    bt->total_tiles = static_cast<uint32_t>(map.size());
+    ok = !map.empty() && hip_ok(hipMalloc(&bt->d_tile_map, sizeof(uint2) * map.size())) &&
+         hip_ok(hipMemcpyAsync(bt->d_tile_map, map.data(), sizeof(uint2) * map.size(),
+                               hipMemcpyHostToDevice, st)) &&
+         hip_ok(hipStreamSynchronize(st));
+    if (!ok) {
+      ssa_batch_destroy(bt);
+      (void)hipGetLastError();
+      return SSA_OUT_OF_MEMORY;
+    }
+  }
   // Capture the launch sequence into one graph.
   hipStream_t cs = nullptr, side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;

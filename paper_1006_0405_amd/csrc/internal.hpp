@@ -109,6 +109,10 @@ hipError_t launch_fft_forward(const double *x, double *y, int count, const launc
                               const twtab_host &tw, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_carry(const task *d_tasks, int ntasks, uint32_t max_tiles, int digit_bits,
                         hipStream_t s, const timing_hook *hk = nullptr);
+// Carries over an explicit list of (task index, tile) pairs, one workgroup each
+// (ntiles >= 1 entries in d_map; every product's tiles consecutive, ascending).
+hipError_t launch_carry_map(const task *d_tasks, const uint2 *d_map, uint32_t ntiles,
+                            int digit_bits, hipStream_t s, const timing_hook *hk = nullptr);
 hipError_t launch_status(const task *d_tasks, int ntasks, int *d_status, hipStream_t s,
                          const timing_hook *hk = nullptr);
 hipError_t launch_directed_probe(int op, const double *a, const double *b, const double *c,

@@ -1114,12 +1114,9 @@ __device__ uint32_t lookback(uint32_t *tiles, uint32_t tile, uint32_t G, uint32_
 // grid = (max tiles, tasks), CARRY_THREADS threads, tile = blockIdx.x.  The tile's coefficients
 // (with 8 before it) are staged in LDS by coalesced loads first, so the six
 // overlapping reads per position hit LDS and each lane issues few global loads.
-__global__ __launch_bounds__(CARRY_THREADS) void k_carry(const task *tasks, int bits) {
+__device__ __forceinline__ void carry_tile(const task &tk, uint32_t tile, int bits) {
   __shared__ uint32_t sh_waves[CARRY_THREADS / 64];
   __shared__ unsigned long long sC[CARRY_TILE + 8];
-  const task tk = tasks[gridDim.y - 1 - blockIdx.y];  // last written first
-  const uint32_t tile = blockIdx.x;
-  if (tile >= tk.ntiles) return;
   const bool failed = (tk.st->too_wide + tk.st->internal) != 0u;
   const long long p0 = static_cast<long long>(tile) * CARRY_TILE;
   const long long base = p0 - 8;
@@ -1152,6 +1149,24 @@ __global__ __launch_bounds__(CARRY_THREADS) void k_carry(const task *tasks, int 
   auto C = [&](long long q) -> unsigned long long { return sC[q - base]; };
   auto tc = [&](uint32_t G, uint32_t P) { return lookback(tk.tiles, tile, G, P, &tk.st->carry_err); };
   carry_block<CARRY_CHUNKS>(C, p0, nout, tk.out, failed, tc, sh_waves);
+}
+
+// grid = (max tiles, tasks); workgroups past a product's last tile exit at once.
+__global__ __launch_bounds__(CARRY_THREADS) void k_carry(const task *tasks, int bits) {
+  const task tk = tasks[gridDim.y - 1 - blockIdx.y];  // last written first
+  const uint32_t tile = blockIdx.x;
+  if (tile >= tk.ntiles) return;
+  carry_tile(tk, tile, bits);
+}
+
+// grid = (number of tiles): workgroup x takes tile map[x].y of task map[x].x.
+// The map lists every tile of every product once, each product's tiles
+// consecutive and in increasing order (the look-back's dispatch order), so
+// products of uneven lengths launch no idle workgroups.
+__global__ __launch_bounds__(CARRY_THREADS) void k_carry_map(const task *tasks, const uint2 *map,
+                                                            int bits) {
+  const uint2 m = map[blockIdx.x];
+  carry_tile(tasks[m.x], m.y, bits);
 }
 
 // Final status per product: 0 ok, 1 too wide, 4 device error, 5 internal.
@@ -1507,6 +1522,15 @@ hipError_t launch_carry(const task *d_tasks, int ntasks, uint32_t max_tiles, int
                         hipStream_t s, const timing_hook *hk) {
   mark(hk, KIND_CARRY, 0);
   hipLaunchKernelGGL(k_carry, dim3(max_tiles, ntasks), dim3(CARRY_THREADS), 0, s, d_tasks,
+                     digit_bits);
+  mark(hk, KIND_CARRY, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_carry_map(const task *d_tasks, const uint2 *d_map, uint32_t ntiles,
+                            int digit_bits, hipStream_t s, const timing_hook *hk) {
+  mark(hk, KIND_CARRY, 0);
+  hipLaunchKernelGGL(k_carry_map, dim3(ntiles), dim3(CARRY_THREADS), 0, s, d_tasks, d_map,
                      digit_bits);
   mark(hk, KIND_CARRY, 1);
   return hipGetLastError();
