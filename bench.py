@@ -166,7 +166,7 @@ def measure_batch(binding, torch, digit_bits, steps, precision="fp64", A=None, B
                 int.from_bytes(B[i].tobytes(), "little")).to_bytes(len(A[i]) + len(B[i]), "little")
         assert status[i] != binding.SSA_OK or bt.OUT[i].cpu().numpy().tobytes() == want, i
     stats = bt.stats()
-    for _ in range(2):
+    for _ in range(5):  # warm-up after the host-side checks left the GPU idle
         bt.run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -631,7 +631,7 @@ def main():
         result["per_fft_length_base256"] = measure_per_n(binding, torch)
 
     if not args.no_batch:
-        steps = max(3, args.steps // 10)
+        steps = max(10, args.steps // 2)
         for bits, base in ((8, "base256"), (4, "base16")):
             r64 = measure_batch(binding, torch, bits, steps)
             r32 = measure_batch(binding, torch, bits, steps, precision="fp32_fallback")
