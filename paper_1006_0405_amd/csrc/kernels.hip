@@ -476,11 +476,12 @@ __device__ __forceinline__ void small_body(const task &tk, int bits, int mode, i
 // marked products that the attempt certified return at once.  The decision is
 // read from the statistics on the device, so a captured launch sequence holds
 // the fallback unconditionally.
-// At 2^12 points a workgroup is 8 waves with 72 KB of LDS: two fit a CU only at
-// four waves per SIMD, so the packed kernel's registers are capped at 128 (a
-// few spill; 36% more products per second than one workgroup per CU).
+// The packed kernel's registers are capped at 128 (four waves per SIMD; a few
+// values spill).  At 2^12 points a workgroup is 8 waves with 72 KB of LDS, and
+// two fit a CU only at four waves per SIMD: 36% more products per second than
+// at the uncapped 137 registers; 5-7% more at 2^9..2^11.
 template <int LOG_N, int bits, int pack, class E>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(LOG_N == 12 && pack == 1 ? 4 : 1)))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(pack == 1 ? 4 : 1)))
 void k_small(const task *tasks, int mode, int fp32, int rerun, int hooks, twtab T, double *dbg) {
   extern __shared__ double2 hbuf[];
   __shared__ cert_shared sh;
