@@ -762,7 +762,7 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
   E v[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) v[r] = mr_load<E>(mr_of(tk.ya, log_n), row + j + r * M8);
-  fft8_group<LOG_N2, WAVE, true>(v, j, hown, 0, T);
+  fft8_group<LOG_N2, WAVE, (LOG_N2 > 9)>(v, j, hown, 0, T);  // twiddle prefetch for long rows
   // Each pair {k, -k} of the two rows needs one product: C_{-k} = conj(C_k)
   // (the coefficients are real).  Elements k2 < N2/2 (r < 4) compute it from
   // their partner's value, and hand it to the partner, whose element lies in
@@ -826,9 +826,11 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
 }
 
 template <int LOG_N2, class E>
-// Three waves per SIMD: the register budget is capped at 168 (a few values spill
-// to scratch for the longest rows), which measured faster than two waves.
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k_row_pair(const task *tasks, int log_n1, int G, twtab T) {
+// Rows of up to 2^9 points: four waves per SIMD (registers capped at 128, a few
+// values spill) without the twiddle prefetch of the row DFT, 4% faster at
+// N = 2^18 than three waves with it.  Longer rows: three waves (168 registers)
+// with the prefetch, which measured faster than two.
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(LOG_N2 <= 9 ? 4 : 3))) void k_row_pair(const task *tasks, int log_n1, int G, twtab T) {
   extern __shared__ double2 hbuf[];
   const uint32_t z = enter_mode<E>();
   const task tk = after_mode(tasks, z)[gridDim.y - 1 - blockIdx.y];  // last written first
