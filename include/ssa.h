@@ -144,12 +144,25 @@ size_t ssa_fft_size(size_t na, size_t nb, int digit_bits);
 ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
                            const ssa_plan_opts *opts, void *stream);
 
-/* Release a plan and everything it allocated.  NULL is ignored. */
+/* Release a plan and everything it allocated (twiddle table, scratch, pinned
+ * staging); waits for the plan's stream first.  Batches created from the plan
+ * must be destroyed before it.  NULL is ignored. */
 void ssa_plan_destroy(ssa_plan *plan);
 
-/* z = a * b.  a: na bytes, b: nb bytes, out: na + nb bytes (device).  Runs on
- * the plan's stream and synchronises it; *status (host) receives the product's
- * ssa_status.  On any status other than SSA_OK, out is zero-filled. */
+/* z = a * b (section 2, long multiplication box: x in Z_b^n, y in Z_b^m ->
+ * z in Z_b^{n+m}), computed by the Schoenhage-Strassen box of section 2.4: the
+ * fast convolution of section 2.3 over complex intervals (section 2.5), then
+ * certification of every coefficient and the carry loop.
+ *  - a: na bytes, b: nb bytes, out: na + nb bytes, all device memory owned by
+ *    the caller; 1 <= na <= max_na and 1 <= nb <= max_nb of the plan, else
+ *    SSA_INVALID_ARGUMENT.  Leading zero bytes and zero operands are allowed.
+ *  - *status (host) receives the outcome.  SSA_OK: out holds the exact product
+ *    (its top byte may be 0).  SSA_ENCLOSURE_TOO_WIDE: some enclosure held
+ *    several integers in every run the plan allows (section 1: report an
+ *    error; the refine_* options add runs), out is zero-filled.
+ *    SSA_INTERNAL_ERROR: an enclosure excluded every integer, which rigorous
+ *    arithmetic cannot produce; out is zero-filled.
+ *  - Runs on the plan's stream and synchronises it; allocates nothing. */
 ssa_status ssa_mul(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
                    uint8_t *out, ssa_status *status);
 
@@ -170,7 +183,20 @@ ssa_status ssa_plan_set_fp32_policy(ssa_plan *plan, int max_coeffs, int force_fa
  * normal certification.  SSA_INVALID_ARGUMENT for another value. */
 ssa_status ssa_plan_force_too_wide(ssa_plan *plan, int on);
 
-/* Statistics of the last ssa_mul on this plan. */
+/* Test hook for the impossible-enclosure path: with index >= 0, certification
+ * of coefficient `index` (in the plan's digits) first lowers that enclosure's
+ * upper bound by 1, so that an enclosure of radius < 1/2 no longer holds any
+ * integer; such a product reports SSA_INTERNAL_ERROR (stats.internal = 1) with a
+ * zero-filled output.  The plan's certify_mode is replaced by the one-integer
+ * rule while the hook is on.  index = -1 turns it off; ssa_plan_force_too_wide
+ * takes precedence.  Affects ssa_mul calls and batches created while it is on.
+ * SSA_INVALID_ARGUMENT for index < -1 or above 2^30. */
+ssa_status ssa_plan_corrupt_bound(ssa_plan *plan, long long index);
+
+/* Statistics of the last ssa_mul on this plan (host copy): the largest
+ * real-part radius of the coefficient enclosures (the width of section 2.5's
+ * intervals, halved and rounded up), the half-integer and failure counts, the
+ * transform length and which run produced the result.  No device work. */
 ssa_status ssa_get_stats(const ssa_plan *plan, ssa_stats *stats_host);
 
 /* Batches: `count` independent products of uneven lengths, each within the
@@ -200,7 +226,10 @@ ssa_status ssa_batch_run_timed(ssa_batch *batch, int *status_dev);
  * Synchronises the plan's stream. */
 ssa_status ssa_batch_kernel_times(ssa_batch *batch, double *ms_host, int *launches_host);
 
-/* Convenience: create, run, synchronise, destroy. */
+/* Convenience: create, run, synchronise, destroy.  Each product is certified
+ * on its own (section 1's per-instance detection): one product's too-wide
+ * enclosure sets only its own status (device array of `count` ints) and
+ * zero-fills only its own output.  Allocates the batch's scratch for the call. */
 ssa_status ssa_mul_batch(ssa_plan *plan, size_t count, const uint8_t *const *a, const size_t *na,
                          const uint8_t *const *b, const size_t *nb, uint8_t *const *out,
                          int *status_dev);
@@ -249,7 +278,10 @@ ssa_status ssa_plan_get_config(const ssa_plan *plan, int log_n, ssa_launch_confi
 ssa_status ssa_plan_set_config(ssa_plan *plan, int log_n, const ssa_launch_config *cfg_host);
 /* Times every valid shape with inv_cols == cols for transforms of length
  * 2^log_n (12 < log_n <= the plan's largest) on `count` synthetic products of
- * that length (device memory allocated for the call and released), then, from
+ * that length in the digits such products run in (fp64_digit_bits when the
+ * plan sets it, else digit_bits; SSA_INVALID_ARGUMENT when the plan's operand
+ * limits allow no product of that length) (device memory allocated for the
+ * call and released), then, from
  * the fastest, every other inv_cols and after that every other cols; keeps the
  * fastest in the plan and returns it with its time per batch of `count`
  * products (milliseconds) and the number of shapes tried.  Synchronises the
@@ -280,6 +312,27 @@ ssa_status ssa_twiddle_table(const ssa_plan *plan, double *tab_dev, double *e_ho
  * Synchronises the stream. */
 ssa_status ssa_probe_directed(int op, const double *a, const double *b, const double *c,
                               double *out, size_t n, void *stream);
+
+/* The device certification step (section 1: the unique integer in each
+ * enclosure, else an error) on caller-supplied enclosures, for testing it
+ * against the CPU oracle.
+ *  - enc_dev (device, read): n x 4 doubles {re_lo, re_hi, im_lo, im_hi},
+ *    1 <= n <= 2^31.  Entries i < L are coefficient enclosures; entries
+ *    L <= i < n are padded-tail enclosures, which must contain 0 in both parts.
+ *  - mode: SSA_CERTIFY_ONE_INTEGER or SSA_CERTIFY_HALF_INTEGER.
+ *  - c_dev (device, written, may be NULL when L = 0): L int64 coefficients, 0
+ *    where an entry is not certified.
+ *  - cls_dev (device, written, nullable): n ints, the entry's outcome: 0 one
+ *    integer, 1 several integers (too wide), 5 impossible (no integer, a single
+ *    negative one or one of 2^52 and more, an imaginary part or a tail entry
+ *    excluding 0), plus 16 when the real part contains a half-integer.
+ *  - stats_host (host, written): status (SSA_INTERNAL_ERROR over
+ *    SSA_ENCLOSURE_TOO_WIDE over SSA_OK), max_radius (largest RU((re_hi -
+ *    re_lo)/2) over i < L), half_int, too_wide and internal counts.
+ * Allocates a few bytes of device memory for the call and synchronises the
+ * stream (NULL = default).  SSA_INVALID_ARGUMENT for bad sizes or mode. */
+ssa_status ssa_probe_certify(const double *enc_dev, size_t n, size_t L, int mode, int64_t *c_dev,
+                             int *cls_dev, ssa_stats *stats_host, void *stream);
 
 #ifdef __cplusplus
 }

@@ -414,7 +414,7 @@ std::vector<P<T>> naive_fft(int k, const std::vector<P<T>> &x, const std::vector
   size_t stride = (size_t(1) << ktop) / M;
   for (size_t i = 0; i < H; ++i) {
     P<T> w = Tw[i * stride];
-    if (inverse) w.im = -w.im;
+    if (inverse && g_mutation != 9) w.im = -w.im;  // planted 9: inverse keeps forward roots
     P<T> t{w.re * O[i].re - w.im * O[i].im, w.re * O[i].im + w.im * O[i].re};
     X[i] = P<T>{E[i].re + t.re, E[i].im + t.im};
     X[i + H] = P<T>{E[i].re - t.re, E[i].im - t.im};

@@ -39,7 +39,8 @@ EXPORTS = ("ssa_fft_size", "ssa_plan_create", "ssa_plan_destroy", "ssa_mul", "ss
            "ssa_mul_batch", "ssa_debug_enclosures", "ssa_twiddle_table", "ssa_probe_directed",
            "ssa_batch_run_timed", "ssa_batch_kernel_times", "ssa_plan_get_config",
            "ssa_plan_set_config", "ssa_plan_autotune", "ssa_plan_set_fp32_policy",
-           "ssa_fft_forward", "ssa_plan_force_too_wide")
+           "ssa_fft_forward", "ssa_plan_force_too_wide", "ssa_plan_corrupt_bound",
+           "ssa_probe_certify")
 KERNEL_KINDS = ("small", "col_fwd", "row", "col_inv", "carry", "status")
 
 
@@ -132,6 +133,11 @@ def lib():
         L.ssa_fft_forward.restype = ctypes.c_int
         L.ssa_fft_forward.argtypes = [_vp, ctypes.c_int, _sz, _vp, _vp, ctypes.POINTER(ctypes.c_int),
                                       _vp]
+        L.ssa_plan_corrupt_bound.restype = ctypes.c_int
+        L.ssa_plan_corrupt_bound.argtypes = [_vp, ctypes.c_longlong]
+        L.ssa_probe_certify.restype = ctypes.c_int
+        L.ssa_probe_certify.argtypes = [_vp, _sz, _sz, ctypes.c_int, _vp, _vp,
+                                        ctypes.POINTER(Stats), _vp]
         L.ssa_probe_directed.restype = ctypes.c_int
         L.ssa_probe_directed.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]
         _lib = L
@@ -190,6 +196,7 @@ class Plan:
         self.handle = h
         self.max_na, self.max_nb = max_na, max_nb
         self.refine_digits = bool(refine_digits)
+        self.fp64_digit_bits = int(fp64_digit_bits)
 
     def close(self):
         if self.handle:
@@ -219,15 +226,21 @@ class Plan:
         _check(lib().ssa_get_stats(self.handle, ctypes.byref(s)), "ssa_get_stats")
         return s.as_dict()
 
-    def set_fp32_policy(self, max_log_n, force_fail=False):
-        """FP32 first attempt for transforms up to 2^max_log_n (0: never);
-        force_fail makes every attempt fail (tests the FP64 re-run)."""
-        _check(lib().ssa_plan_set_fp32_policy(self.handle, int(max_log_n), int(bool(force_fail))),
+    def set_fp32_policy(self, max_coeffs, force_fail=False):
+        """FP32 first attempt for products with at most max_coeffs coefficients
+        (L = digits(a) + digits(b) - 1, 0: never) whose transform fits one
+        workgroup; force_fail makes every attempt fail (tests the FP64 re-run)."""
+        _check(lib().ssa_plan_set_fp32_policy(self.handle, int(max_coeffs), int(bool(force_fail))),
                "ssa_plan_set_fp32_policy")
 
     def force_too_wide(self, on=True):
         """Test hook: certification refuses every coefficient while on."""
         _check(lib().ssa_plan_force_too_wide(self.handle, int(bool(on))), "ssa_plan_force_too_wide")
+
+    def corrupt_bound(self, index):
+        """Test hook: certification lowers the upper bound of coefficient
+        `index` by 1 (-1 turns it off)."""
+        _check(lib().ssa_plan_corrupt_bound(self.handle, int(index)), "ssa_plan_corrupt_bound")
 
     def debug_enclosures(self, a, b):
         """(status, out, enclosures N x 4 float64 {re_lo, re_hi, im_lo, im_hi})."""
@@ -260,9 +273,10 @@ class Plan:
         if cache:
             import json
             props = torch.cuda.get_device_properties(self.device)
-            key = "%s/log_n=%d/digit_bits=%d/separate=%d/arithmetic=%s" % (
+            key = "%s/log_n=%d/digit_bits=%d/separate=%d/arithmetic=%s/precision=%s/fp64_digit_bits=%d" % (
                 getattr(props, "gcnArchName", props.name), log_n, self.digit_bits,
-                int(self.separate_transforms), self.arithmetic)
+                int(self.separate_transforms), self.arithmetic, self.precision,
+                self.fp64_digit_bits)
             try:
                 table = json.load(open(cache))
             except (OSError, ValueError):
@@ -386,6 +400,21 @@ def probe_directed(op, a, b, c, stream=None):
     _check(lib().ssa_probe_directed(op, a.data_ptr(), b.data_ptr(), c.data_ptr(), out.data_ptr(),
                                     a.numel(), _vp(_stream_handle(stream))), "ssa_probe_directed")
     return out
+
+
+def probe_certify(enc, L, mode=SSA_CERTIFY_ONE_INTEGER, stream=None):
+    """The device certification step on enclosures enc (n x 4 float64,
+    {re_lo, re_hi, im_lo, im_hi}) of which the first L are coefficients.
+    Returns (stats dict, int64 coefficients[L], per-entry outcome int32[n])."""
+    e = torch.as_tensor(enc, dtype=torch.float64).reshape(-1, 4).cuda().contiguous()
+    n = e.shape[0]
+    c = torch.zeros(max(L, 1), dtype=torch.int64, device=e.device)
+    cls = torch.full((n,), -1, dtype=torch.int32, device=e.device)
+    st = Stats()
+    _check(lib().ssa_probe_certify(e.data_ptr(), n, L, mode, c.data_ptr(), cls.data_ptr(),
+                                   ctypes.byref(st), _vp(_stream_handle(stream))),
+           "ssa_probe_certify")
+    return st.as_dict(), c[:L].cpu().numpy(), cls.cpu().numpy()
 
 
 def mul(a, b, digit_bits=8, certify_mode=SSA_CERTIFY_ONE_INTEGER):

@@ -10,6 +10,7 @@ import os
 import re
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -34,15 +35,21 @@ def _run(cmd, verbose):
     return r
 
 
+def _isa_of(src, verbose):
+    asm = os.path.join("/tmp", f"ssa_isa_{os.getpid()}_{src}.s")
+    _run(["hipcc", *COMMON, "--offload-device-only", "-S", os.path.join(CSRC, src), "-o", asm],
+         verbose)
+    text = open(asm).read()
+    os.remove(asm)
+    return text
+
+
 def check_isa(verbose=False):
     """Generate device assembly and verify the MODE-register discipline."""
     bad = []
-    for src in SOURCES:
-        asm = os.path.join("/tmp", f"ssa_isa_{os.getpid()}_{src}.s")
-        _run(["hipcc", *COMMON, "--offload-device-only", "-S", os.path.join(CSRC, src), "-o", asm],
-             verbose)
-        text = open(asm).read()
-        os.remove(asm)
+    with ThreadPoolExecutor(len(SOURCES)) as ex:
+        texts = list(ex.map(lambda s: _isa_of(s, verbose), SOURCES))
+    for src, text in zip(SOURCES, texts):
         for line in text.splitlines():
             t = line.strip()
             if re.match(r"s_setreg|s_round_mode|s_denorm_mode", t) and t != OWN_MODE_WRITE:
@@ -52,11 +59,10 @@ def check_isa(verbose=False):
 
 
 def build(verbose=False, check=True):
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join("/tmp", f"ssa_{os.getpid()}_{src}.o")
-        _run(["hipcc", *COMMON, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+    objs = [os.path.join("/tmp", f"ssa_{os.getpid()}_{src}.o") for src in SOURCES]
+    with ThreadPoolExecutor(len(SOURCES)) as ex:
+        list(ex.map(lambda so: _run(["hipcc", *COMMON, "-c", os.path.join(CSRC, so[0]), "-o", so[1]],
+                                    verbose), zip(SOURCES, objs)))
     tmp = LIB + ".tmp"
     _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     for o in objs:

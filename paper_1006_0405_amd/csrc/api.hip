@@ -27,7 +27,7 @@ int ceil_log2(uint64_t v) {
   return k;
 }
 
-// Transform length exponent for L coefficients (zero padding up to 2^8).
+// Transform length exponent for L coefficients (zero padding up to 2^SMALL_MIN_LOG = 2^9).
 int log_n_for(uint64_t L) { return std::max(ceil_log2(L), SMALL_MIN_LOG); }
 
 uint64_t digits(size_t n, int bits) { return bits == 4 ? 2 * uint64_t(n) : uint64_t(n); }
@@ -138,6 +138,7 @@ struct ssa_plan {
   uint32_t fp32_max_L = 0;  // FP32 first attempt for products with L <= this (0: never)
   int hooks = 0;         // test hooks (HOOK_FORCE_FP32_FAIL)
   int force_too_wide = 0;  // test hook: certification refuses every coefficient
+  int corrupt_index = -1;  // test hook: coefficient whose upper bound is lowered by 1 (-1: off)
   int split_graph = 1;     // batch graphs run each multi-pass class as two concurrent halves
   size_t max_na = 0, max_nb = 0;
   int log_nmax = 0;
@@ -229,7 +230,9 @@ hipError_t enqueue_class(const ssa_plan *p, const task *d_tasks, int n, int n32,
                          double *dbg, hipStream_t s, const timing_hook *hk = nullptr,
                          int bits = 0) {
   if (bits == 0) bits = p->opts.digit_bits;
-  const int mode = p->force_too_wide ? CERT_FORCE_TOO_WIDE : p->opts.certify_mode;
+  const int mode = p->force_too_wide        ? CERT_FORCE_TOO_WIDE
+                   : p->corrupt_index >= 0 ? CERT_CORRUPT_BASE + p->corrupt_index
+                                           : p->opts.certify_mode;
   const int pack = p->opts.separate_transforms ? 0 : 1;
   const int arith = p->opts.arithmetic;
   if (log_n <= SMALL_MAX_LOG) {
@@ -241,7 +244,14 @@ hipError_t enqueue_class(const ssa_plan *p, const task *d_tasks, int n, int n32,
     if (e != hipSuccess) return e;
     return launch_small(d_tasks, n, log_n, bits, mode, pack, arith, 0, 1, 0, tw_of(p), dbg, s, hk);
   }
-  return launch_multipass(d_tasks, n, log_n, p->cfg[log_n], bits, mode, tw_of(p), dbg, s, hk);
+  // the multi-pass kernels index products by a grid dimension (at most 65535)
+  constexpr int MAX_GRID_PRODUCTS = 65535;
+  for (int k0 = 0; k0 < n; k0 += MAX_GRID_PRODUCTS) {
+    const hipError_t e = launch_multipass(d_tasks + k0, std::min(MAX_GRID_PRODUCTS, n - k0), log_n,
+                                          p->cfg[log_n], bits, mode, tw_of(p), dbg, s, hk);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // One product with the given digit size; the FP32 attempt only in the plan's own.
@@ -476,6 +486,12 @@ ssa_status ssa_plan_force_too_wide(ssa_plan *plan, int on) {
   return SSA_OK;
 }
 
+ssa_status ssa_plan_corrupt_bound(ssa_plan *plan, long long index) {
+  if (!plan || index < -1 || index > (1ll << 30)) return SSA_INVALID_ARGUMENT;
+  plan->corrupt_index = static_cast<int>(index);
+  return SSA_OK;
+}
+
 ssa_status ssa_get_stats(const ssa_plan *plan, ssa_stats *stats_host) {
   if (!plan || !stats_host) return SSA_INVALID_ARGUMENT;
   *stats_host = plan->last;
@@ -492,6 +508,30 @@ ssa_status ssa_twiddle_table(const ssa_plan *plan, double *tab_dev, double *e_ho
     return SSA_DEVICE_ERROR;
   *e_host = plan->e;
   *log_ntab_host = plan->log_ntab;
+  return SSA_OK;
+}
+
+ssa_status ssa_probe_certify(const double *enc_dev, size_t n, size_t L, int mode, int64_t *c_dev,
+                             int *cls_dev, ssa_stats *stats_host, void *stream) {
+  if (!enc_dev || !stats_host || n == 0 || n > (size_t(1) << 31) || L > n || (L > 0 && !c_dev) ||
+      (mode != SSA_CERTIFY_ONE_INTEGER && mode != SSA_CERTIFY_HALF_INTEGER))
+    return SSA_INVALID_ARGUMENT;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  dev_stats *st = nullptr;
+  if (!hip_ok(hipMalloc(&st, sizeof(dev_stats)))) {
+    (void)hipGetLastError();
+    return SSA_OUT_OF_MEMORY;
+  }
+  dev_stats h{};
+  const bool ok =
+      hip_ok(hipMemsetAsync(st, 0, sizeof(dev_stats), s)) &&
+      hip_ok(launch_certify_probe(enc_dev, static_cast<uint32_t>(n), static_cast<uint32_t>(L), mode,
+                                  reinterpret_cast<unsigned long long *>(c_dev), cls_dev, st, s)) &&
+      hip_ok(hipMemcpyAsync(&h, st, sizeof(dev_stats), hipMemcpyDeviceToHost, s)) &&
+      hip_ok(hipStreamSynchronize(s));
+  (void)hipFree(st);
+  if (!ok) return SSA_DEVICE_ERROR;
+  *stats_host = to_public(h, 0);
   return SSA_OK;
 }
 
@@ -865,7 +905,10 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
   if (!plan || !best || !best_ms_host || log_n <= SMALL_MAX_LOG || log_n > plan->log_nmax ||
       count < 1 || count > 4096)
     return SSA_INVALID_ARGUMENT;
-  const int bits = plan->opts.digit_bits;
+  // the digit size a multi-pass product of this plan runs in (the FP32 attempt
+  // is single-workgroup, so with fp64_digit_bits every such product goes to
+  // the FP64 path with those digits)
+  const int bits = plan->opts.fp64_digit_bits ? plan->opts.fp64_digit_bits : plan->opts.digit_bits;
   const int pack = plan->opts.separate_transforms ? 0 : 1;
   const int arith = plan->opts.arithmetic;
   // equal operands as long as the plan allows, at most 2^(log_n - 1) digits each;
@@ -907,6 +950,10 @@ ssa_status ssa_plan_autotune(ssa_plan *plan, int log_n, int count, ssa_launch_co
   ssa_batch *bt = nullptr;
   ssa_status r = ssa_batch_create(plan, count, pa.data(), na.data(), pb.data(), nb.data(),
                                   po.data(), &bt);
+  if (r == SSA_OK && (bt->h_tasks[0].log_n != static_cast<uint32_t>(log_n) || bt->bits[0] != bits)) {
+    ssa_batch_destroy(bt);  // the products would not run at the length being tuned
+    r = SSA_INVALID_ARGUMENT;
+  }
   if (r != SSA_OK) {
     (void)hipFree(dops);
     (void)hipFree(dout);

@@ -43,7 +43,10 @@ struct task {
 enum { ARITH_RECT = 0, ARITH_DISC = 1, ARITH_POINT = 2 };
 
 // CERT_FORCE_TOO_WIDE: test hook, every coefficient counts as too wide.
-enum { CERT_ONE_INTEGER = 0, CERT_HALF_INTEGER = 1, CERT_FORCE_TOO_WIDE = 2 };
+// Modes from CERT_CORRUPT_BASE on: test hook, one-integer certification with
+// the upper bound of coefficient (mode - CERT_CORRUPT_BASE) lowered by 1
+// before it is certified (an enclosure that no longer holds its integer).
+enum { CERT_ONE_INTEGER = 0, CERT_HALF_INTEGER = 1, CERT_FORCE_TOO_WIDE = 2, CERT_CORRUPT_BASE = 4 };
 
 // Tile of the carry scan: 4 wavefronts x 8 chunks of 64 positions (half the LDS of 16 chunks, so twice the resident tiles: 15% faster).
 static constexpr int CARRY_THREADS = 256;
@@ -117,5 +120,11 @@ hipError_t launch_status(const task *d_tasks, int ntasks, int *d_status, hipStre
                          const timing_hook *hk = nullptr);
 hipError_t launch_directed_probe(int op, const double *a, const double *b, const double *c,
                                  double *out, size_t n, hipStream_t s);
+// Certification of n caller-supplied enclosures (n x 4 doubles {re_lo, re_hi,
+// im_lo, im_hi}) of which the first L are coefficients: coefficients to c
+// (L entries), per-entry outcome to cls (nullable), totals accumulated into
+// *st (zeroed by the caller).
+hipError_t launch_certify_probe(const double *enc, uint32_t n, uint32_t L, int mode,
+                                unsigned long long *c, int *cls, dev_stats *st, hipStream_t s);
 
 }  // namespace ssa

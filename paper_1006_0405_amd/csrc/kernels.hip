@@ -73,6 +73,8 @@ __device__ __forceinline__ unsigned long long certify_re(double n, double h, boo
     if (!(n >= 0.0 && h >= 0.0 && im0)) acc.internal++;
     return 0ull;
   }
+  if (mode >= CERT_CORRUPT_BASE && i == static_cast<uint32_t>(mode - CERT_CORRUPT_BASE))
+    h = ru_add(h, -1.0);  // test hook: this enclosure no longer holds its integer
   const double rad = ru_mul(ru_add(n, h), 0.5);
   acc.rad = rad > acc.rad ? rad : acc.rad;
   const double m = -dfloor(n);  // ceil(lo)
@@ -1208,6 +1210,38 @@ __global__ void k_probe(int op, const double *a, const double *b, const double *
   out[i] = r;
 }
 
+// Certification of caller-supplied enclosures, one per thread: the same
+// certify() and cert_reduce() as the product kernels.  cls[i] (when given) is
+// the entry's outcome, 0 one integer, 1 several, 5 impossible, plus 16 when
+// the real part contains a half-integer.
+__global__ __launch_bounds__(256) void k_certify_probe(const double *enc, uint32_t n, uint32_t L,
+                                                       int mode, unsigned long long *c, int *cls,
+                                                       dev_stats *st) {
+  __shared__ cert_shared sh;
+  const uint32_t z = enter_round_up();
+  enc = after_mode(enc, z);
+  if (threadIdx.x == 0) sh = cert_shared{0ull, 0ull, 0u, 0u};
+  __syncthreads();
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  cert_acc acc{0.0, 0u, 0u, 0u};
+  if (i < n) {
+    const ci e = gld(reinterpret_cast<const ci *>(enc), i);  // {re_lo, re_hi, im_lo, im_hi}
+    const ci v{-e.rn, e.rh, -e.in, e.ih};
+    const unsigned long long cv = certify(v, i, L, mode, acc);
+    if (i < L) c[i] = cv;
+    if (cls != nullptr)
+      cls[i] = (acc.internal ? 5 : (acc.too_wide ? 1 : 0)) | (acc.half ? 16 : 0);
+  }
+  cert_reduce(sh, acc);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicMax(&st->max_rad_bits, sh.rad_bits);
+    if (sh.half) atomicAdd(&st->half_int, sh.half);
+    if (sh.too_wide) atomicAdd(&st->too_wide, sh.too_wide);
+    if (sh.internal) atomicAdd(&st->internal, sh.internal);
+  }
+}
+
 // Statuses from batch slot order back to the caller's order.
 __global__ void k_scatter(const int *slot_status, const int *order, int n, int *out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1548,6 +1582,13 @@ hipError_t launch_status(const task *d_tasks, int ntasks, int *d_status, hipStre
   hipLaunchKernelGGL(k_status, dim3((ntasks + 255) / 256), dim3(256), 0, s, d_tasks, ntasks,
                      d_status);
   mark(hk, KIND_STATUS, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_certify_probe(const double *enc, uint32_t n, uint32_t L, int mode,
+                                unsigned long long *c, int *cls, dev_stats *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_certify_probe, dim3((n + 255) / 256), dim3(256), 0, s, enc, n, L, mode, c,
+                     cls, st);
   return hipGetLastError();
 }
 

@@ -6,8 +6,9 @@ unique, so parity with the oracle's DFT (oracle.dft, radix-2 recursion in
 fesetround interval arithmetic) is checked by intersection: both enclose the
 same exact DFT, so every GPU interval must meet the oracle's.  Exact values
 (DFT special cases of the section 2.2 lemma, and 200-bit mpmath sums at sampled
-indices) must lie inside the GPU enclosures.  The maximum half-widths are
-reported side by side.
+indices) must lie inside the GPU enclosures.  The GPU enclosures must also be
+no wider than the oracle's, element by element (above a tiny floor where the
+oracle's are exact); the maximum half-widths are reported side by side.
 """
 import mpmath
 import numpy as np
@@ -48,6 +49,38 @@ def assert_intersects(g, o):
         assert not bad.any(), "disjoint enclosures at %s" % np.argwhere(bad)[:5].tolist()
 
 
+def assert_not_wider(g, o, x, log_n, factor=1.0):
+    """Width bound: at every element and in both parts, the GPU half-width is at
+    most the larger of `factor` times the oracle's and an a priori floor
+    6 log2(N) u sum_n |x_n| (u = 2^-53): a linear accumulation of one rounding
+    bound per stage over the largest possible magnitude.  Both enclosures sit
+    near that floor for thin inputs (the GPU's widest is 0.4-0.8 of it at
+    2^13..2^18, the oracle's about the same), so an enclosure a few times too
+    wide fails.  factor = 1 for thin inputs (the digits of a product).  For
+    inputs that are already wide the rectangles' wrapping decides the width,
+    and it depends on the factorisation: the four-step radix-8 form rotates
+    some elements by roots whose rectangular hull grows more than on the
+    radix-2 path (up to 1.26 times the oracle's width measured at 2^13..2^16),
+    so such inputs take factor 1.5."""
+    mag = float(np.sum(np.max(np.abs(x), axis=1)))
+    floor = 6 * log_n * 2.0 ** -53 * mag
+    narrower, ratio, widest = 0, 0.0, 0.0
+    for lo, hi in ((0, 1), (2, 3)):
+        hg = (g[:, hi] - g[:, lo]) / 2
+        ho = (o[:, hi] - o[:, lo]) / 2
+        bad = hg > np.maximum(factor * ho, floor)
+        assert not bad.any(), "GPU enclosure too wide at %s: %s vs oracle %s (floor %.3g)" % (
+            np.argwhere(bad)[:5].ravel().tolist(), hg[bad][:5].tolist(), ho[bad][:5].tolist(), floor)
+        narrower += int(np.sum(hg <= ho))
+        widest = max(widest, float(np.max(hg)))
+        big = ho > floor
+        if big.any():
+            ratio = max(ratio, float(np.max(hg[big] / ho[big])))
+    print("GPU half-width <= oracle's at %.1f%% of the parts; widest %.3g = %.2f of the floor "
+          "%.3g; largest ratio to the oracle above the floor %.3f"
+          % (100.0 * narrower / (2 * len(g)), widest, widest / floor, floor, ratio))
+
+
 def half_width(e):
     return max(float(np.max(e[..., 1] - e[..., 0])), float(np.max(e[..., 3] - e[..., 2]))) / 2
 
@@ -72,6 +105,7 @@ def test_fft_meets_oracle(log_n, shape):
     for v in range(3):
         o = oracle.dft(log_n, x[v])
         assert_intersects(g[v], o)
+        assert_not_wider(g[v], o, x[v], log_n, factor=1.5 if v == 2 else 1.0)
         print("N=2^%d vector %d: half-width GPU %.3g, oracle %.3g" % (log_n, v, half_width(g[v]),
                                                                      half_width(o)))
     plan.close()
@@ -138,6 +172,7 @@ def test_fft_2p18_bench_shape_meets_oracle():
     for shape in ((9, 4, 1), (9, 4, 2)):
         g = gpu_fft(plan, x, log_n, shape)[0]
         assert_intersects(g, o)
+        assert_not_wider(g, o, x[0], log_n)
         print("2^18 shape %s: half-width GPU %.3g, oracle %.3g" % (shape, half_width(g),
                                                                    half_width(o)))
     plan.close()

@@ -4,8 +4,9 @@ An SSA_FP32_FALLBACK plan runs the forward transform of small products in FP32
 midpoint-radius discs (circular containment sets, paper section 4) and
 re-runs on the device, in FP64, every product that the attempt could not
 certify.  Whatever the path, a returned product must be the exact integer
-product (bit-exact against CPython's integers and the oracle); the statistics
-say which products needed the re-run.
+product: bit-exact against CPython's integers and, with the same status,
+against the oracle (whose FP64 radius is printed beside the attempt's); the
+statistics say which products needed the re-run.
 """
 import numpy as np
 import pytest
@@ -40,8 +41,14 @@ def test_fp32_attempt_products_exact(digit_bits, separate):
         st, out = plan.mul(a, b)
         assert st == binding.SSA_OK, (na, nb, binding.STATUS_NAMES.get(st, st))
         assert np.array_equal(_np(out), int_product(a, b)), (na, nb)
-        assert plan.stats()["fp32_attempt"] == 1
-        used.append((na, nb, plan.stats()["fallback"]))
+        ost, oout, orad, _ = oracle.mul(a, b, digit_bits=digit_bits)
+        assert st == ost and np.array_equal(_np(out), oout), (na, nb)
+        s_ = plan.stats()
+        assert s_["fp32_attempt"] == 1
+        used.append((na, nb, s_["fallback"]))
+        print("%5d x %5d: fallback %d, radius GPU %.3e (FP32 attempt%s), oracle FP64 %.3e"
+              % (na, nb, s_["fallback"], s_["max_radius"],
+                 " then FP64 re-run" if s_["fallback"] else "", orad))
     print("fallback per size:", used)
     # the smallest products certify in FP32 without the re-run
     limit = 8 if digit_bits == 8 else 130
@@ -131,6 +138,17 @@ def test_fp32_batch_base16_exact_and_reports_fallback():
     for (a, b), s in zip(zip(A, B), st):
         assert s["fp32_attempt"] == int(2 * (len(a) + len(b)) - 1 <= 511)
         assert s["fallback"] <= s["fp32_attempt"]
+    # the attempted products against the oracle (base 16, FP64): same status and
+    # bytes; the radii side by side
+    rows = []
+    for i, s in enumerate(st):
+        if s["fp32_attempt"]:
+            ost, oout, orad, _ = oracle.mul(A[i], B[i], digit_bits=4)
+            assert ost == binding.SSA_OK and np.array_equal(_np(bt.OUT[i]), oout), i
+            rows.append((s["max_radius"], orad))
+    assert len(rows) == n_try
+    print("attempted products: GPU radius max %.3e, oracle radius max %.3e"
+          % (max(r for r, _ in rows), max(o for _, o in rows)))
     bt.close()
     plan.close()
 

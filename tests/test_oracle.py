@@ -445,6 +445,32 @@ def test_naive_single_precision_sometimes_wrong_at_120_digits():
     assert 0 < wrong < trials // 4
 
 
+@pytest.mark.parametrize("n,kind", [(1024, "random"), (75000, "random"), (75000, "all_ff")])
+def test_naive_double_matches_the_integer_product(n, kind):
+    """The naive double-precision variant (section 3's "double naive" SSA) rounds
+    every coefficient to the nearest integer without a certificate; at these
+    sizes its rounding errors stay far below 1/2, so its products are exact."""
+    a, b = pair(11, n) if kind == "random" else (np.full(n, 255, np.uint8), np.full(n, 255, np.uint8))
+    st, out = oracle.mul_naive(a, b)
+    assert st == oracle.ST_OK
+    assert np.array_equal(out, int_product(a, b))
+    st, out = oracle.mul_naive(a, b, digit_bits=4)
+    assert np.array_equal(out, int_product(a, b))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 16])
+def test_naive_single_precision_exact_on_short_operands(n):
+    """Short products (coefficients below 2^20, transforms of at most 32 points)
+    leave single precision's rounding errors far below 1/2."""
+    for s in range(40):
+        a, b = pair(7000 + s, n)
+        _, out = oracle.mul_naive(a, b, precision="f32")
+        assert np.array_equal(out, int_product(a, b)), s
+    f = np.full(n, 255, np.uint8)
+    _, out = oracle.mul_naive(f, f, precision="f32")
+    assert np.array_equal(out, int_product(f, f))
+
+
 def test_single_precision_intervals_never_certify_a_wrong_product():
     for s in range(40):
         n = [8, 16, 24, 40, 64, 120][s % 6]
@@ -486,6 +512,27 @@ def _pin_battery():
     except AssertionError:
         failed.append("rounding")
     return failed
+
+
+def _naive_battery():
+    """The naive variants' pins: double at 1024 bytes, single on short operands."""
+    failed = []
+    a, b = pair(11, 1024)
+    if not np.array_equal(oracle.mul_naive(a, b)[1], int_product(a, b)):
+        failed.append("naive_f64")
+    a, b = pair(7000, 16)
+    if not np.array_equal(oracle.mul_naive(a, b, precision="f32")[1], int_product(a, b)):
+        failed.append("naive_f32")
+    return failed
+
+
+def test_planted_mistake_in_the_naive_variant_is_caught():
+    """Mistake 9: the naive inverse transform keeps the forward roots."""
+    assert _naive_battery() == []
+    with oracle.mutation(9):
+        failed = _naive_battery()
+    assert failed == ["naive_f64", "naive_f32"], failed
+    assert _naive_battery() == []
 
 
 @pytest.mark.parametrize("mutation", [1, 2, 3, 4, 5, 6, 7, 8])
