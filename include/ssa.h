@@ -166,6 +166,31 @@ void ssa_plan_destroy(ssa_plan *plan);
 ssa_status ssa_mul(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
                    uint8_t *out, ssa_status *status);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the product
+ * of ssa_mul for a plan with the default options (FP64 rectangles, base 256,
+ * packed transform, one-integer certification), with no plan and no
+ * allocation.  The scratch (twiddle table, transform array, coefficients,
+ * statistics, carry state, descriptor: about 18.1 MiB) is one static device
+ * array per GPU, held until the process ends.
+ *  - a: na bytes, b: nb bytes, out: na + nb bytes, status_dev: one int, all
+ *    device memory owned by the caller.  na + nb - 1 <= 2^18 (75,000-byte
+ *    operands fit; transforms of at most 2^18 points), else
+ *    SSA_INVALID_ARGUMENT and nothing is enqueued.
+ *  - *status_dev receives the ssa_status of the product (SSA_OK: out holds the
+ *    exact product; otherwise out is zero-filled), stream-ordered on `stream`;
+ *    nothing is synchronised, so the call can be captured into a graph.
+ *  - The first call on a device (the current one) finds that device's array,
+ *    builds the twiddle table in it and synchronises `stream` once; it must not
+ *    be made under stream capture (SSA_INVALID_ARGUMENT).  Later calls only
+ *    enqueue kernels.
+ *  - All calls on one GPU share its array, and every call leaves its contents
+ *    there: calls that overlap on one GPU (different streams, or different
+ *    host threads without ordering) race and give wrong products.  Order them
+ *    on one stream. */
+ssa_status ssa_mul_noalloc(const uint8_t *a, size_t na, const uint8_t *b, size_t nb, uint8_t *out,
+                           int *status_dev, void *stream);
+
 /* FP32 policy of an SSA_FP32_FALLBACK plan (the length predictor): a product
  * tries FP32 first when its coefficient count L = digits(a) + digits(b) - 1 is
  * at most max_coeffs (0 <= max_coeffs <= 4096; 0 disables the attempt) and its

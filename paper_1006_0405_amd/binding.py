@@ -40,7 +40,7 @@ EXPORTS = ("ssa_fft_size", "ssa_plan_create", "ssa_plan_destroy", "ssa_mul", "ss
            "ssa_batch_run_timed", "ssa_batch_kernel_times", "ssa_plan_get_config",
            "ssa_plan_set_config", "ssa_plan_autotune", "ssa_plan_set_fp32_policy",
            "ssa_fft_forward", "ssa_plan_force_too_wide", "ssa_plan_corrupt_bound",
-           "ssa_probe_certify")
+           "ssa_probe_certify", "ssa_mul_noalloc")
 KERNEL_KINDS = ("small", "col_fwd", "row", "col_inv", "carry", "status")
 
 
@@ -96,6 +96,8 @@ def lib():
         L.ssa_plan_destroy.argtypes = [_vp]
         L.ssa_mul.restype = ctypes.c_int
         L.ssa_mul.argtypes = [_vp, _vp, _sz, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_int)]
+        L.ssa_mul_noalloc.restype = ctypes.c_int
+        L.ssa_mul_noalloc.argtypes = [_vp, _sz, _vp, _sz, _vp, _vp, _vp]
         L.ssa_get_stats.restype = ctypes.c_int
         L.ssa_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
         L.ssa_batch_create.restype = ctypes.c_int
@@ -415,6 +417,22 @@ def probe_certify(enc, L, mode=SSA_CERTIFY_ONE_INTEGER, stream=None):
                                    ctypes.byref(st), _vp(_stream_handle(stream))),
            "ssa_probe_certify")
     return st.as_dict(), c[:L].cpu().numpy(), cls.cpu().numpy()
+
+
+def mul_noalloc(a, b, out, status, stream=None):
+    """ssa_mul_noalloc: the product of a and b (uint8 device tensors) into out
+    (len(a) + len(b) bytes) with its status into status (an int32 device tensor
+    of at least one element), stream-ordered, without any allocation by the
+    library.  Nothing is synchronised."""
+    for t in (a, b, out):
+        if t.dtype != torch.uint8 or t.device.type != "cuda" or not t.is_contiguous():
+            raise SsaError("operands and output must be contiguous uint8 device tensors")
+    if out.numel() != a.numel() + b.numel():
+        raise SsaError("out must hold len(a) + len(b) bytes")
+    if status.dtype != torch.int32 or status.device.type != "cuda" or status.numel() < 1:
+        raise SsaError("status must be an int32 device tensor")
+    _check(lib().ssa_mul_noalloc(a.data_ptr(), a.numel(), b.data_ptr(), b.numel(), out.data_ptr(),
+                                 status.data_ptr(), _vp(_stream_handle(stream))), "ssa_mul_noalloc")
 
 
 def mul(a, b, digit_bits=8, certify_mode=SSA_CERTIFY_ONE_INTEGER):

@@ -39,7 +39,9 @@ static_assert(ARITH_RECT == SSA_ARITH_RECT && ARITH_DISC == SSA_ARITH_DISC &&
                   ARITH_POINT == SSA_ARITH_NAIVE,
               "the kernels' element types follow ssa_plan_opts.arithmetic");
 
-launch_cfg default_cfg(int log_n, int pack, int arith) {
+}  // namespace
+
+launch_cfg ssa::default_launch_cfg(int log_n, int pack, int arith) {
   launch_cfg c;
   c.log_n1 = log_n / 2;
   c.log_n2 = log_n - c.log_n1;
@@ -56,6 +58,8 @@ launch_cfg default_cfg(int log_n, int pack, int arith) {
     c.rows = std::max(1, std::min(N1, 256 / t));
   return c;
 }
+
+namespace {
 
 // A launch shape is usable when every workgroup has at most 512 threads in
 // whole wavefronts, its LDS (exchange buffers with one spare slot per 8
@@ -126,10 +130,6 @@ ssa_stats to_public(const dev_stats &s, int log_n) {
 bool kernels_configured = false;
 
 }  // namespace
-
-namespace ssa {
-hipError_t set_kernel_attributes();
-}
 
 struct ssa_plan {
   int device = 0;
@@ -382,7 +382,7 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
   p->log_nref = log_nref;
   p->log_ntab = log_nalloc;
   for (int l = SMALL_MAX_LOG + 1; l <= MAX_LOG_N; ++l)
-    p->cfg[l] = default_cfg(l, o.separate_transforms ? 0 : 1, o.arithmetic);
+    p->cfg[l] = default_launch_cfg(l, o.separate_transforms ? 0 : 1, o.arithmetic);
   const size_t N = size_t(1) << log_nalloc;
   const size_t ntiles = (max_na + max_nb + CARRY_TILE - 1) / CARRY_TILE;
   bool ok = hip_ok(hipMalloc(&p->tab, sizeof(double2) << (p->log_ntab + 1))) &&  // level tables

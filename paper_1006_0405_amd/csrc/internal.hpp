@@ -73,6 +73,11 @@ struct launch_cfg {
                // plain row pass)
 };
 
+// Default launch shape of the three-pass path for N = 2^log_n.
+launch_cfg default_launch_cfg(int log_n, int pack, int arith);
+// Raises every product kernel's dynamic-LDS limit (once per process).
+hipError_t set_kernel_attributes();
+
 struct twtab_host {
   const double2 *tab;
   int log_ntab;
