@@ -48,7 +48,7 @@ typedef enum {
 } ssa_status;
 
 enum { SSA_FP64 = 0, SSA_FP32_FALLBACK = 1 };
-enum { SSA_ARITH_RECT = 0, SSA_ARITH_DISC = 1, SSA_ARITH_NAIVE = 2 };
+enum { SSA_ARITH_RECT = 0, SSA_ARITH_DISC = 1, SSA_ARITH_NAIVE = 2, SSA_ARITH_NAIVE32 = 3 };
 enum { SSA_CERTIFY_ONE_INTEGER = 0, SSA_CERTIFY_HALF_INTEGER = 1 };
 
 typedef struct {
@@ -93,7 +93,14 @@ typedef struct {
                               stats.max_radius holds the largest distance of a
                               coefficient to its integer.  Needs precision SSA_FP64,
                               the packed transform, no refinement, and launch shapes
-                              without the persistent row pass.                    */
+                              without the persistent row pass.
+                              SSA_ARITH_NAIVE32: NOT RIGOROUS, the same in single
+                              precision (float complex points, the double twiddles
+                              rounded to float): the arithmetic of section 1's remark
+                              that a naive single-precision transform is sometimes
+                              wrong at 120 base-256 digits.  Only products whose
+                              transform fits one workgroup (ssa_fft_size <= 4096);
+                              the plan's max_na + max_nb must give such a length.  */
   int refine_disc;         /* 0 (default) or 1 with arithmetic = SSA_ARITH_RECT and the
                               packed transform: ssa_mul re-runs a product whose
                               rectangular enclosures hold several integers once more
@@ -109,6 +116,21 @@ typedef struct {
                               re-runs a base-256 product refused as too wide with
                               base-16 digits (stats.refined = 1); batches report the
                               base-256 outcome.  Same products.                    */
+  int exact_fallback;      /* 0 (default): a product that every interval run refuses
+                              is reported as SSA_ENCLOSURE_TOO_WIDE (section 1:
+                              report an error).  1: ssa_mul then computes it with
+                              the other algorithm section 1 allows: the same fast
+                              convolution (section 2.3) by a number-theoretic
+                              transform over Z_p, p = 2^64 - 2^32 + 1, exact by
+                              construction (the idea of the paper's second,
+                              finite-ring Schoenhage-Strassen algorithm), so such a
+                              plan's ssa_mul always returns the product
+                              (stats.refined = 3).  Products whose interval
+                              transform would exceed 2^22 points go to it directly,
+                              up to na + nb - 1 <= 2^27 bytes; the plan allocates 56
+                              bytes per point of that transform.  Not with
+                              SSA_ARITH_NAIVE.  Batches never use it (products
+                              beyond 2^22 points are rejected there).            */
 } ssa_plan_opts;
 
 typedef struct {
@@ -125,7 +147,9 @@ typedef struct {
   int refined;         /* 1: base 256 was too wide and the base-16 re-run produced it
                           (plans with refine_digits or fp64_digit_bits); 2: the
                           rectangles were too wide
-                          and the re-run in discs produced it (refine_disc)          */
+                          and the re-run in discs produced it (refine_disc); 3: the
+                          exact number-theoretic transform produced it
+                          (exact_fallback; max_radius is then 0)                */
 } ssa_stats;
 
 typedef struct ssa_plan ssa_plan;
@@ -140,7 +164,9 @@ size_t ssa_fft_size(size_t na, size_t nb, int digit_bits);
  * all device scratch once (ssa_mul never allocates), generates the certified
  * twiddle table on the device (section 2.2 half-angle recurrence) and waits
  * for it.  opts may be NULL (FP64, base 256, one-integer certification).
- * On error *plan is NULL. */
+ * The longest product's transform (ssa_fft_size) must be at most 2^22 points,
+ * or with opts->exact_fallback at most 2^27 base-256 points (na, nb <= 2^31);
+ * SSA_INVALID_ARGUMENT otherwise.  On error *plan is NULL. */
 ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
                            const ssa_plan_opts *opts, void *stream);
 
@@ -165,6 +191,15 @@ void ssa_plan_destroy(ssa_plan *plan);
  *  - Runs on the plan's stream and synchronises it; allocates nothing. */
 ssa_status ssa_mul(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
                    uint8_t *out, ssa_status *status);
+
+/* z = a * b by long multiplication (section 2.1, LM box), the O(na nb) method
+ * that section 3 times the Schoenhage-Strassen product against: the exact
+ * column sums s_i = sum_j a_j b_{i-j} (integer dot products on the GPU), then
+ * the LM box's carry loop as the library's carry scan.  Exact, so *status is
+ * always SSA_OK.  Same arguments, limits, stream and synchronisation as
+ * ssa_mul; uses the plan's scratch (any plan), allocates nothing. */
+ssa_status ssa_mul_long(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
+                        uint8_t *out, ssa_status *status);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the product

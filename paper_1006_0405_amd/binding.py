@@ -27,9 +27,11 @@ STATUS_NAMES = {0: "OK", 1: "ENCLOSURE_TOO_WIDE", 2: "INVALID_ARGUMENT", 3: "OUT
 SSA_FP64 = 0
 SSA_FP32_FALLBACK = 1
 PRECISIONS = {"fp64": SSA_FP64, "fp32_fallback": SSA_FP32_FALLBACK}
-SSA_ARITH_RECT, SSA_ARITH_DISC, SSA_ARITH_NAIVE = 0, 1, 2
-# "naive": the non-rigorous point-arithmetic baseline (products not certified)
-ARITHMETICS = {"rect": SSA_ARITH_RECT, "disc": SSA_ARITH_DISC, "naive": SSA_ARITH_NAIVE}
+SSA_ARITH_RECT, SSA_ARITH_DISC, SSA_ARITH_NAIVE, SSA_ARITH_NAIVE32 = 0, 1, 2, 3
+# "naive", "naive32": the non-rigorous point-arithmetic baselines in double and
+# single precision (products not certified)
+ARITHMETICS = {"rect": SSA_ARITH_RECT, "disc": SSA_ARITH_DISC, "naive": SSA_ARITH_NAIVE,
+               "naive32": SSA_ARITH_NAIVE32}
 SSA_CERTIFY_ONE_INTEGER = 0
 SSA_CERTIFY_HALF_INTEGER = 1
 
@@ -40,7 +42,7 @@ EXPORTS = ("ssa_fft_size", "ssa_plan_create", "ssa_plan_destroy", "ssa_mul", "ss
            "ssa_batch_run_timed", "ssa_batch_kernel_times", "ssa_plan_get_config",
            "ssa_plan_set_config", "ssa_plan_autotune", "ssa_plan_set_fp32_policy",
            "ssa_fft_forward", "ssa_plan_force_too_wide", "ssa_plan_corrupt_bound",
-           "ssa_probe_certify", "ssa_mul_noalloc")
+           "ssa_probe_certify", "ssa_mul_noalloc", "ssa_mul_long")
 KERNEL_KINDS = ("small", "col_fwd", "row", "col_inv", "carry", "status")
 
 
@@ -52,7 +54,8 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("digit_bits", ctypes.c_int),
                 ("certify_mode", ctypes.c_int), ("separate_transforms", ctypes.c_int),
                 ("refine_digits", ctypes.c_int), ("arithmetic", ctypes.c_int),
-                ("refine_disc", ctypes.c_int), ("fp64_digit_bits", ctypes.c_int)]
+                ("refine_disc", ctypes.c_int), ("fp64_digit_bits", ctypes.c_int),
+                ("exact_fallback", ctypes.c_int)]
 
 
 class LaunchConfig(ctypes.Structure):
@@ -98,6 +101,8 @@ def lib():
         L.ssa_mul.argtypes = [_vp, _vp, _sz, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_int)]
         L.ssa_mul_noalloc.restype = ctypes.c_int
         L.ssa_mul_noalloc.argtypes = [_vp, _sz, _vp, _sz, _vp, _vp, _vp]
+        L.ssa_mul_long.restype = ctypes.c_int
+        L.ssa_mul_long.argtypes = [_vp, _vp, _sz, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_int)]
         L.ssa_get_stats.restype = ctypes.c_int
         L.ssa_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
         L.ssa_batch_create.restype = ctypes.c_int
@@ -177,7 +182,8 @@ class Plan:
 
     def __init__(self, max_na, max_nb, digit_bits=8, certify_mode=SSA_CERTIFY_ONE_INTEGER,
                  separate_transforms=False, precision="fp64", stream=None, device=None,
-                 refine_digits=False, arithmetic="rect", refine_disc=False, fp64_digit_bits=0):
+                 refine_digits=False, arithmetic="rect", refine_disc=False, fp64_digit_bits=0,
+                 exact_fallback=False):
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.digit_bits = digit_bits
@@ -190,7 +196,8 @@ class Plan:
         self.arithmetic = arithmetic
         opts = PlanOpts(PRECISIONS[precision], digit_bits, certify_mode,
                         int(bool(separate_transforms)), int(bool(refine_digits)),
-                        ARITHMETICS[arithmetic], int(bool(refine_disc)), int(fp64_digit_bits))
+                        ARITHMETICS[arithmetic], int(bool(refine_disc)), int(fp64_digit_bits),
+                        int(bool(exact_fallback)))
         h = _vp()
         with torch.cuda.device(self.device):
             _check(lib().ssa_plan_create(ctypes.byref(h), max_na, max_nb, ctypes.byref(opts),
@@ -221,6 +228,17 @@ class Plan:
         st = ctypes.c_int(-1)
         _check(lib().ssa_mul(self.handle, a.data_ptr(), a.numel(), b.data_ptr(), b.numel(),
                              out.data_ptr(), ctypes.byref(st)), "ssa_mul")
+        return st.value, out
+
+    def mul_long(self, a, b, out=None):
+        """Long multiplication (ssa_mul_long): (status, out) like mul."""
+        a = _dev_u8(a, self.device)
+        b = _dev_u8(b, self.device)
+        if out is None:
+            out = torch.empty(a.numel() + b.numel(), dtype=torch.uint8, device=self.device)
+        st = ctypes.c_int(-1)
+        _check(lib().ssa_mul_long(self.handle, a.data_ptr(), a.numel(), b.data_ptr(), b.numel(),
+                                  out.data_ptr(), ctypes.byref(st)), "ssa_mul_long")
         return st.value, out
 
     def stats(self):

@@ -15,7 +15,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libssa.so")
-SOURCES = ["api.hip", "kernels.hip", "twiddle.hip", "noalloc.hip"]
+SOURCES = ["api.hip", "kernels.hip", "twiddle.hip", "noalloc.hip", "ntt.hip", "lm.hip"]
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",

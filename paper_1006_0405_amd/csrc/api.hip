@@ -20,6 +20,30 @@ using namespace ssa;
 namespace {
 
 constexpr int MAX_LOG_N = 22;  // N1 = N2 = 2^11: 1024-thread column and 512-thread row passes
+// Longest exact (number-theoretic) transform: base-256 operands of up to
+// 2^26 bytes each; every coefficient stays below 2^26 255^2 < 2^42.
+constexpr int MAX_NTT_LOG = 27;
+constexpr uint64_t NTT_P = 0xFFFFFFFF00000001ull;  // 2^64 - 2^32 + 1
+
+uint64_t host_mulmod(uint64_t a, uint64_t b) {
+  return static_cast<uint64_t>(static_cast<unsigned __int128>(a) * b % NTT_P);
+}
+uint64_t host_powmod(uint64_t w, uint64_t e) {
+  uint64_t r = 1;
+  for (; e; e >>= 1, w = host_mulmod(w, w))
+    if (e & 1) r = host_mulmod(r, w);
+  return r;
+}
+// A root of unity of order exactly 2^K in Z_p: 7^((p - 1) / 2^32) has order
+// 2^32 (its 2^31-th power is -1), and its 2^(32 - K)-th power has order 2^K.
+// Returns 0 if that check fails.
+uint64_t ntt_root(int K) {
+  const uint64_t w32 = host_powmod(7, (NTT_P - 1) >> 32);
+  if (host_powmod(w32, uint64_t(1) << 31) != NTT_P - 1) return 0;
+  const uint64_t w = host_powmod(w32, uint64_t(1) << (32 - K));
+  if (K > 0 && host_powmod(w, uint64_t(1) << (K - 1)) != NTT_P - 1) return 0;
+  return w;
+}
 
 int ceil_log2(uint64_t v) {
   int k = 0;
@@ -36,7 +60,7 @@ uint64_t digits(size_t n, int bits) { return bits == 4 ? 2 * uint64_t(n) : uint6
 // thread): C adjacent columns per column-pass workgroup (256 threads, 512 for
 // N1 = 2^11), and G rows (or row pairs) per row-pass workgroup.
 static_assert(ARITH_RECT == SSA_ARITH_RECT && ARITH_DISC == SSA_ARITH_DISC &&
-                  ARITH_POINT == SSA_ARITH_NAIVE,
+                  ARITH_POINT == SSA_ARITH_NAIVE && ARITH_POINT32 == SSA_ARITH_NAIVE32,
               "the kernels' element types follow ssa_plan_opts.arithmetic");
 
 }  // namespace
@@ -143,6 +167,8 @@ struct ssa_plan {
   size_t max_na = 0, max_nb = 0;
   int log_nmax = 0;
   int log_nref = 0;  // refine_digits: largest base-16 re-run transform (0: none)
+  int log_nntt = 0;  // exact_fallback: longest exact transform (0: none)
+  uint64_t *ntt_lv = nullptr;  // exact_fallback: roots of unity of Z_p by level
   // twiddles
   double2 *tab = nullptr;
   int log_ntab = 0;
@@ -195,6 +221,7 @@ void free_plan(ssa_plan *p) {
   (void)hipFree(p->tab);
   (void)hipFree(p->ebits);
   (void)hipFree(p->roots);
+  (void)hipFree(p->ntt_lv);
   (void)hipFree(p->ya);
   (void)hipFree(p->yb);
   (void)hipFree(p->c);
@@ -294,12 +321,53 @@ ssa_status run_once(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b, 
   return SSA_OK;
 }
 
+// The exact last resort: the product by a number-theoretic transform over
+// Z_p with base-256 digits, then the same carry scan.  Always certified.
+ssa_status run_ntt(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
+                   uint8_t *out, ssa_status *status) {
+  const uint64_t L = uint64_t(na) + nb - 1;
+  const int log_n = log_n_for(L);
+  if (log_n > p->log_nntt) return SSA_INVALID_ARGUMENT;
+  task &t = *p->h_task;
+  std::memset(&t, 0, sizeof(t));
+  t.a = a;
+  t.b = b;
+  t.out = out;
+  t.na = t.nda = static_cast<uint32_t>(na);
+  t.nb = t.ndb = static_cast<uint32_t>(nb);
+  t.L = static_cast<uint32_t>(L);
+  t.log_n = static_cast<uint32_t>(log_n);
+  t.ya = p->ya;
+  t.c = p->c;
+  t.st = p->st;
+  t.tiles = p->tiles;
+  t.ntiles = static_cast<uint32_t>((na + nb + CARRY_TILE - 1) / CARRY_TILE);
+  const uint64_t ninv = host_powmod(uint64_t(1) << log_n, NTT_P - 2);
+  hipStream_t s = p->stream;
+  if (!hip_ok(hipMemcpyAsync(p->d_task, p->h_task, sizeof(task), hipMemcpyHostToDevice, s)) ||
+      !hip_ok(launch_ntt_product(p->d_task, t, log_n, p->ntt_lv, ninv, s)) ||
+      !hip_ok(launch_carry(p->d_task, 1, t.ntiles, 8, s)) ||
+      !hip_ok(hipMemcpyAsync(p->h_stats, p->st, sizeof(dev_stats), hipMemcpyDeviceToHost, s)) ||
+      !hip_ok(hipStreamSynchronize(s)))
+    return SSA_DEVICE_ERROR;
+  p->last = to_public(*p->h_stats, log_n);
+  p->last.refined = 3;
+  *status = static_cast<ssa_status>(p->last.status);
+  return SSA_OK;
+}
+
 ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
                       uint8_t *out, double *dbg, ssa_status *status) {
   if (!p || !a || !b || !out || !status || na == 0 || nb == 0 || na > p->max_na ||
       nb > p->max_nb)
     return SSA_INVALID_ARGUMENT;
   const int bits0 = dbg ? p->opts.digit_bits : route_bits(p, na, nb);
+  // products longer than the interval kernels reach go straight to the exact
+  // transform (plans with exact_fallback only: others never admit them)
+  if (log_n_for(digits(na, bits0) + digits(nb, bits0) - 1) > p->log_nmax) {
+    if (dbg || !p->opts.exact_fallback) return SSA_INVALID_ARGUMENT;
+    return run_ntt(p, a, na, b, nb, out, status);
+  }
   ssa_status r = run_once(p, a, na, b, nb, out, dbg, status, bits0);
   // refinement in discs: the same transform once more with circular enclosures
   if (r == SSA_OK && *status == SSA_ENCLOSURE_TOO_WIDE && p->opts.refine_disc && !dbg) {
@@ -327,6 +395,9 @@ ssa_status run_single(ssa_plan *p, const uint8_t *a, size_t na, const uint8_t *b
     r = run_once(p, a, na, b, nb, out, dbg, status, p->opts.digit_bits);
     p->last.refined = 1;
   }
+  // every interval run refused: the exact transform (section 1: another algorithm)
+  if (r == SSA_OK && *status == SSA_ENCLOSURE_TOO_WIDE && p->opts.exact_fallback && !dbg)
+    r = run_ntt(p, a, na, b, nb, out, status);
   return r;
 }
 
@@ -351,17 +422,27 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
       (o.separate_transforms != 0 && o.separate_transforms != 1) ||
       (o.refine_digits != 0 && (o.refine_digits != 1 || o.digit_bits != 8)) ||
       (o.arithmetic != SSA_ARITH_RECT && o.arithmetic != SSA_ARITH_DISC &&
-       o.arithmetic != SSA_ARITH_NAIVE) ||
+       o.arithmetic != SSA_ARITH_NAIVE && o.arithmetic != SSA_ARITH_NAIVE32) ||
       (o.arithmetic != SSA_ARITH_RECT && o.separate_transforms != 0) ||
-      (o.arithmetic == SSA_ARITH_NAIVE && (o.precision != SSA_FP64 || o.refine_digits != 0)) ||
+      ((o.arithmetic == SSA_ARITH_NAIVE || o.arithmetic == SSA_ARITH_NAIVE32) &&
+       (o.precision != SSA_FP64 || o.refine_digits != 0)) ||
       (o.refine_disc != 0 && (o.refine_disc != 1 || o.arithmetic != SSA_ARITH_RECT ||
                               o.separate_transforms != 0)) ||
       (o.fp64_digit_bits != 0 && (o.fp64_digit_bits != 8 || o.digit_bits != 4 ||
-                                  o.precision != SSA_FP32_FALLBACK)))
+                                  o.precision != SSA_FP32_FALLBACK)) ||
+      (o.exact_fallback != 0 &&
+       (o.exact_fallback != 1 || o.arithmetic == SSA_ARITH_NAIVE || o.arithmetic == SSA_ARITH_NAIVE32)))
     return SSA_INVALID_ARGUMENT;
   const uint64_t L = digits(max_na, o.digit_bits) + digits(max_nb, o.digit_bits) - 1;
-  const int log_nmax = log_n_for(L);
-  if (log_nmax > MAX_LOG_N) return SSA_INVALID_ARGUMENT;
+  // the exact transform takes base-256 digits
+  const int log_nntt = o.exact_fallback ? log_n_for(uint64_t(max_na) + max_nb - 1) : 0;
+  if (log_nntt > MAX_NTT_LOG || max_na > (size_t(1) << 31) || max_nb > (size_t(1) << 31))
+    return SSA_INVALID_ARGUMENT;
+  // longer products than the interval kernels reach: only with the exact transform
+  if (log_n_for(L) > MAX_LOG_N && !o.exact_fallback) return SSA_INVALID_ARGUMENT;
+  // single precision points: the single-workgroup kernel only
+  if (o.arithmetic == SSA_ARITH_NAIVE32 && log_n_for(L) > SMALL_MAX_LOG) return SSA_INVALID_ARGUMENT;
+  const int log_nmax = std::min(log_n_for(L), MAX_LOG_N);
   // the base-16 re-run of refine_digits, as far as a transform of 2^MAX_LOG_N reaches
   const int log_nref =
       o.refine_digits ? std::min(log_n_for(digits(max_na, 4) + digits(max_nb, 4) - 1), MAX_LOG_N) : 0;
@@ -380,23 +461,32 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
   p->max_nb = max_nb;
   p->log_nmax = log_nmax;
   p->log_nref = log_nref;
+  p->log_nntt = log_nntt;
   p->log_ntab = log_nalloc;
   for (int l = SMALL_MAX_LOG + 1; l <= MAX_LOG_N; ++l)
     p->cfg[l] = default_launch_cfg(l, o.separate_transforms ? 0 : 1, o.arithmetic);
   const size_t N = size_t(1) << log_nalloc;
+  const size_t Nntt = log_nntt ? size_t(1) << log_nntt : 0;
   const size_t ntiles = (max_na + max_nb + CARRY_TILE - 1) / CARRY_TILE;
+  // transform array: N interval elements (32 bytes) or four arrays of Nntt
+  // residues (the same 32 bytes per point)
+  const size_t ya_elems = std::max(log_nalloc > SMALL_MAX_LOG ? N : 0, Nntt);
+  static_assert(sizeof(ci) == 4 * sizeof(uint64_t), "an exact product uses four residue arrays");
   bool ok = hip_ok(hipMalloc(&p->tab, sizeof(double2) << (p->log_ntab + 1))) &&  // level tables
             hip_ok(hipMalloc(&p->ebits, sizeof(unsigned long long))) &&
             hip_ok(hipMalloc(&p->roots, twiddle_roots_bytes())) &&
-            hip_ok(hipMalloc(&p->c, sizeof(unsigned long long) * N)) &&
+            hip_ok(hipMalloc(&p->c, sizeof(unsigned long long) * std::max(N, Nntt))) &&
             hip_ok(hipMalloc(&p->st, sizeof(dev_stats))) &&
             hip_ok(hipMalloc(&p->tiles, sizeof(uint32_t) * TILE_WORD_STRIDE * ntiles)) &&
             hip_ok(hipMalloc(&p->d_task, sizeof(task))) &&
             hip_ok(hipHostMalloc(&p->h_task, sizeof(task), hipHostMallocDefault)) &&
             hip_ok(hipHostMalloc(&p->h_stats, sizeof(dev_stats), hipHostMallocDefault));
-  if (ok && log_nalloc > SMALL_MAX_LOG)
-    ok = hip_ok(hipMalloc(&p->ya, sizeof(ci) * N)) &&  // the packed transform needs one array
-         (!o.separate_transforms || hip_ok(hipMalloc(&p->yb, sizeof(ci) * N)));
+  if (ok && ya_elems)
+    ok = hip_ok(hipMalloc(&p->ya, sizeof(ci) * ya_elems));  // the packed transform needs one array
+  if (ok && log_nalloc > SMALL_MAX_LOG && o.separate_transforms)
+    ok = hip_ok(hipMalloc(&p->yb, sizeof(ci) * N));
+  if (ok && log_nntt)
+    ok = hip_ok(hipMalloc(&p->ntt_lv, sizeof(uint64_t) * 2 * Nntt));
   if (!ok) {
     free_plan(p);
     (void)hipGetLastError();
@@ -407,6 +497,8 @@ ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
   ok = hip_ok(hipMemcpyAsync(p->ebits, &eb, sizeof(eb), hipMemcpyHostToDevice, p->stream)) &&
        hip_ok(make_twiddles(p->log_ntab, p->tab + N, p->ebits, p->roots, p->stream)) &&
        hip_ok(make_level_tables(p->log_ntab, p->tab, p->stream)) &&
+       (!log_nntt || (ntt_root(log_nntt) != 0 &&
+                      hip_ok(make_ntt_levels(log_nntt, ntt_root(log_nntt), p->ntt_lv, p->stream)))) &&
        hip_ok(hipMemcpyAsync(&eb, p->ebits, sizeof(eb), hipMemcpyDeviceToHost, p->stream)) &&
        hip_ok(hipStreamSynchronize(p->stream));
   if (!ok) {
@@ -427,6 +519,37 @@ void ssa_plan_destroy(ssa_plan *plan) {
 ssa_status ssa_mul(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
                    uint8_t *out, ssa_status *status) {
   return run_single(plan, a, na, b, nb, out, nullptr, status);
+}
+
+ssa_status ssa_mul_long(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b, size_t nb,
+                        uint8_t *out, ssa_status *status) {
+  ssa_plan *p = plan;
+  if (!p || !a || !b || !out || !status || na == 0 || nb == 0 || na > p->max_na || nb > p->max_nb)
+    return SSA_INVALID_ARGUMENT;
+  const uint64_t L = uint64_t(na) + nb - 1;
+  task &t = *p->h_task;
+  std::memset(&t, 0, sizeof(t));
+  t.a = a;
+  t.b = b;
+  t.out = out;
+  t.na = t.nda = static_cast<uint32_t>(na);
+  t.nb = t.ndb = static_cast<uint32_t>(nb);
+  t.L = static_cast<uint32_t>(L);
+  t.log_n = static_cast<uint32_t>(log_n_for(L));
+  t.c = p->c;
+  t.st = p->st;
+  t.tiles = p->tiles;
+  t.ntiles = static_cast<uint32_t>((na + nb + CARRY_TILE - 1) / CARRY_TILE);
+  hipStream_t s = p->stream;
+  if (!hip_ok(hipMemcpyAsync(p->d_task, p->h_task, sizeof(task), hipMemcpyHostToDevice, s)) ||
+      !hip_ok(launch_long_mul(p->d_task, t, s)) ||
+      !hip_ok(launch_carry(p->d_task, 1, t.ntiles, 8, s)) ||
+      !hip_ok(hipMemcpyAsync(p->h_stats, p->st, sizeof(dev_stats), hipMemcpyDeviceToHost, s)) ||
+      !hip_ok(hipStreamSynchronize(s)))
+    return SSA_DEVICE_ERROR;
+  p->last = to_public(*p->h_stats, 0);
+  *status = static_cast<ssa_status>(p->last.status);
+  return SSA_OK;
 }
 
 ssa_status ssa_debug_enclosures(ssa_plan *plan, const uint8_t *a, size_t na, const uint8_t *b,
@@ -663,6 +786,7 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
     bits[i] = route_bits(plan, na[i], nb[i]);
     const uint64_t L = digits(na[i], bits[i]) + digits(nb[i], bits[i]) - 1;
     lg[i] = log_n_for(L);
+    if (lg[i] > plan->log_nmax) return SSA_INVALID_ARGUMENT;  // exact transform: ssa_mul only
     f32[i] = (bits[i] == plan->opts.digit_bits && fp32_first(plan, L, lg[i])) ? 1 : 0;
   }
   ssa_batch *bt = new (std::nothrow) ssa_batch();

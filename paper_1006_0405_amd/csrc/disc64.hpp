@@ -152,6 +152,39 @@ __device__ __forceinline__ double2 e_word0(const pt &a) { return make_double2(a.
 __device__ __forceinline__ double2 e_word1(const pt &) { return make_double2(0.0, 0.0); }
 __device__ __forceinline__ void e_from_words(pt &a, double2 w0, double2) { a = pt{w0.x, w0.y}; }
 
+// ---- Single-precision point complex numbers (the naive FP32 baseline) ------
+// The paper's section 1 observation concerns this arithmetic: a naive
+// single-precision transform is usually right and sometimes wrong already at
+// 120 base-256 digits.  Plain float complex values, round to nearest, the
+// double twiddles rounded to float; an exchange moves the pair as one 8-byte
+// word (the low half of a 16-byte slot).  Nothing is certified.
+struct pf {
+  float re, im;
+};
+__device__ __forceinline__ pf e_add(const pf &a, const pf &b) { return pf{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ pf e_sub(const pf &a, const pf &b) { return pf{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ pf e_mul_i(const pf &a) { return pf{-a.im, a.re}; }
+__device__ __forceinline__ pf e_mul_negi(const pf &a) { return pf{a.im, -a.re}; }
+__device__ __forceinline__ pf e_conj(const pf &a) { return pf{a.re, -a.im}; }
+__device__ __forceinline__ pf e_scale(const pf &a, double p2) {
+  const float f = static_cast<float>(p2);  // a power of two: exact
+  return pf{a.re * f, a.im * f};
+}
+__device__ __forceinline__ pf e_tw(const pf &a, double c, double s, double) {
+  const float cf = static_cast<float>(c), sf = static_cast<float>(s);
+  return pf{cf * a.re - sf * a.im, sf * a.re + cf * a.im};
+}
+__device__ __forceinline__ pf e_tw_q1(const pf &a, double c, double s, double e) { return e_tw(a, c, s, e); }
+__device__ __forceinline__ pf e_tw_uh(const pf &a, double c, double s, double e) { return e_tw(a, c, s, e); }
+__device__ __forceinline__ double2 e_word0(const pf &a) {
+  return make_double2(__builtin_bit_cast(double, make_float2(a.re, a.im)), 0.0);
+}
+__device__ __forceinline__ double2 e_word1(const pf &) { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ void e_from_words(pf &a, double2 w0, double2) {
+  const float2 f = __builtin_bit_cast(float2, w0.x);
+  a = pf{f.x, f.y};
+}
+
 // Per element type: whether it is an enclosure (rigorous) and how many 16-byte
 // words an LDS exchange moves.
 template <class E> struct e_traits {
@@ -159,6 +192,10 @@ template <class E> struct e_traits {
   static constexpr int words = 2;
 };
 template <> struct e_traits<pt> {
+  static constexpr bool rigorous = false;
+  static constexpr int words = 1;
+};
+template <> struct e_traits<pf> {
   static constexpr bool rigorous = false;
   static constexpr int words = 1;
 };

@@ -66,6 +66,8 @@ __device__ __forceinline__ md e_mul_w8(const md &z, double c8, double e8) { retu
 __device__ __forceinline__ md e_mul_w83(const md &z, double c8, double e8) { return md_tw(z, -c8, c8, e8); }
 __device__ __forceinline__ pt e_mul_w8(const pt &z, double c8, double e8) { return e_tw(z, c8, c8, e8); }
 __device__ __forceinline__ pt e_mul_w83(const pt &z, double c8, double e8) { return e_tw(z, -c8, c8, e8); }
+__device__ __forceinline__ pf e_mul_w8(const pf &z, double c8, double e8) { return e_tw(z, c8, c8, e8); }
+__device__ __forceinline__ pf e_mul_w83(const pf &z, double c8, double e8) { return e_tw(z, -c8, c8, e8); }
 
 template <class E> __device__ __forceinline__ void radix8(E v[8], double c8, double e8) {
   E a[4], b[4];

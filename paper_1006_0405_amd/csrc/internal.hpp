@@ -39,8 +39,9 @@ struct task {
   uint32_t fp32;          // 1: FP32 first attempt, FP64 re-run on failure
 };
 
-// Element types of the transforms (the values of ssa_plan_opts.arithmetic).
-enum { ARITH_RECT = 0, ARITH_DISC = 1, ARITH_POINT = 2 };
+// Element types of the transforms (the values of ssa_plan_opts.arithmetic);
+// single-precision points only in the single-workgroup kernel.
+enum { ARITH_RECT = 0, ARITH_DISC = 1, ARITH_POINT = 2, ARITH_POINT32 = 3 };
 
 // CERT_FORCE_TOO_WIDE: test hook, every coefficient counts as too wide.
 // Modes from CERT_CORRUPT_BASE on: test hook, one-integer certification with
@@ -131,5 +132,16 @@ hipError_t launch_directed_probe(int op, const double *a, const double *b, const
 // *st (zeroed by the caller).
 hipError_t launch_certify_probe(const double *enc, uint32_t n, uint32_t L, int mode,
                                 unsigned long long *c, int *cls, dev_stats *st, hipStream_t s);
+
+// The exact transform (ntt.hip): roots of unity of Z_p, p = 2^64 - 2^32 + 1, by
+// level (lv[2^l + u] = w_{2^l}^u, 2^(K+1) entries, wK of order 2^K), and one
+// product's convolution coefficients into task.c (task.ya: 4 N residues of
+// scratch); the carry scan follows separately.
+hipError_t make_ntt_levels(int K, uint64_t wK, uint64_t *lv, hipStream_t s);
+// Long multiplication (lm.hip): the column sums of task d_task into its
+// coefficients (zeroed first, with the statistics and carry state).
+hipError_t launch_long_mul(const task *d_task, const task &h_task, hipStream_t s);
+hipError_t launch_ntt_product(const task *d_task, const task &h_task, int log_n, const uint64_t *lv,
+                              uint64_t ninv, hipStream_t s);
 
 }  // namespace ssa

@@ -273,10 +273,20 @@ __device__ __forceinline__ pt separated_product(const pt &Z, const pt &W) {
   return pt{A.re * B.re - A.im * B.im, A.re * B.im + A.im * B.re};
 }
 
+// The same in single precision (the naive FP32 baseline).
+__device__ __forceinline__ pf separated_product(const pf &Z, const pf &W) {
+  const pf S = e_add(Z, W), D = e_sub(Z, W);
+  const pf A{0.5f * S.re, 0.5f * S.im}, B{0.5f * D.im, -0.5f * D.re};
+  return pf{A.re * B.re - A.im * B.im, A.re * B.im + A.im * B.re};
+}
+
 // A product's packed input element a + i b from two digits, thin.
 __device__ __forceinline__ void e_thin_pair(ci &z, double da, double db) { z = ci{-da, da, -db, db}; }
 __device__ __forceinline__ void e_thin_pair(md &z, double da, double db) { z = md{da, db, 0.0}; }
 __device__ __forceinline__ void e_thin_pair(pt &z, double da, double db) { z = pt{da, db}; }
+__device__ __forceinline__ void e_thin_pair(pf &z, double da, double db) {
+  z = pf{static_cast<float>(da), static_cast<float>(db)};  // digits below 256: exact
+}
 
 // Real-part and imaginary-part enclosures (negated lower bound, upper bound).
 __device__ __forceinline__ double2 e_re_nh(const ci &z) { return make_double2(z.rn, z.rh); }
@@ -285,6 +295,12 @@ __device__ __forceinline__ double2 e_re_nh(const md &z) { return make_double2(md
 __device__ __forceinline__ double2 e_im_nh(const md &z) { return make_double2(md_im_n(z), md_im_h(z)); }
 __device__ __forceinline__ double2 e_re_nh(const pt &z) { return make_double2(-z.re, z.re); }
 __device__ __forceinline__ double2 e_im_nh(const pt &z) { return make_double2(-z.im, z.im); }
+__device__ __forceinline__ double2 e_re_nh(const pf &z) {
+  return make_double2(-static_cast<double>(z.re), static_cast<double>(z.re));
+}
+__device__ __forceinline__ double2 e_im_nh(const pf &z) {
+  return make_double2(-static_cast<double>(z.im), static_cast<double>(z.im));
+}
 
 // ---------------------------------------------------------------------------
 // k_small: the whole product in one workgroup of N/8 threads, N = 2^log_n,
@@ -296,6 +312,7 @@ __device__ __forceinline__ void mr_to_e(const mr &a, ci &z) { z = mr_to_ci(a); }
 __device__ __forceinline__ void mr_to_e(const mr &a, md &z) {
   z = md{static_cast<double>(a.re), static_cast<double>(a.im), static_cast<double>(a.r)};
 }
+__device__ __forceinline__ void mr_to_e(const mr &a, pf &z) { z = pf{a.re, a.im}; }  // (unused)
 __device__ __forceinline__ void mr_to_e(const mr &a, pt &z) {  // (no FP32 attempt with points)
   z = pt{static_cast<double>(a.re), static_cast<double>(a.im)};
 }
@@ -1266,7 +1283,8 @@ hipError_t set_kernel_attributes() {
   reinterpret_cast<const void *>(&k_small<L, 8, 1, ci>), reinterpret_cast<const void *>(&k_small<L, 4, 1, ci>), \
       reinterpret_cast<const void *>(&k_small<L, 8, 0, ci>), reinterpret_cast<const void *>(&k_small<L, 4, 0, ci>), \
       reinterpret_cast<const void *>(&k_small<L, 8, 1, md>), reinterpret_cast<const void *>(&k_small<L, 4, 1, md>), \
-      reinterpret_cast<const void *>(&k_small<L, 8, 1, pt>), reinterpret_cast<const void *>(&k_small<L, 4, 1, pt>),
+      reinterpret_cast<const void *>(&k_small<L, 8, 1, pt>), reinterpret_cast<const void *>(&k_small<L, 4, 1, pt>), \
+      reinterpret_cast<const void *>(&k_small<L, 8, 1, pf>), reinterpret_cast<const void *>(&k_small<L, 4, 1, pf>),
       SSA_SMALL_LENGTHS(SSA_K_SMALL)
 #undef SSA_K_SMALL
 #define SSA_K_PASS(L)                                                                    \
@@ -1310,7 +1328,7 @@ hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bi
   const int threads = 1 << (log_n - 3);
   const size_t lds = sizeof(double2) * lpad_size(size_t(1) << log_n);
   if (arith != ARITH_RECT && !pack) return hipErrorInvalidValue;  // discs, points: packed only
-  if (arith == ARITH_POINT && fp32) return hipErrorInvalidValue;
+  if ((arith == ARITH_POINT || arith == ARITH_POINT32) && fp32) return hipErrorInvalidValue;
   mark(hk, KIND_SMALL, 0);
   switch (log_n) {
 #define SSA_L(L)                                                                               \
@@ -1326,6 +1344,12 @@ hipError_t launch_small(const task *d_tasks, int ntasks, int log_n, int digit_bi
                          cert_mode, fp32, rerun, hooks, to_dev(tw), dbg);                       \
     else if (arith == ARITH_POINT)                                                              \
       hipLaunchKernelGGL((k_small<L, 4, 1, pt>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
+                         cert_mode, fp32, rerun, hooks, to_dev(tw), dbg);                       \
+    else if (arith == ARITH_POINT32 && digit_bits == 8)                                         \
+      hipLaunchKernelGGL((k_small<L, 8, 1, pf>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
+                         cert_mode, fp32, rerun, hooks, to_dev(tw), dbg);                       \
+    else if (arith == ARITH_POINT32)                                                            \
+      hipLaunchKernelGGL((k_small<L, 4, 1, pf>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
                          cert_mode, fp32, rerun, hooks, to_dev(tw), dbg);                       \
     else if (digit_bits == 8 && pack)                                                           \
       hipLaunchKernelGGL((k_small<L, 8, 1, ci>), dim3(ntasks), dim3(threads), lds, s, d_tasks,  \
@@ -1391,6 +1415,7 @@ hipError_t launch_multipass(const task *d_tasks, int ntasks, int log_n, const la
   if (l1 < 6 || l1 > 11 || l2 < 6 || l2 > 11 || (1 << lc) != cfg.cols) return hipErrorInvalidValue;
   if (cfg.arith != ARITH_RECT && (!cfg.pack || cfg.persist))
     return hipErrorInvalidValue;  // discs and points: packed transform, plain row pass
+  if (cfg.arith == ARITH_POINT32) return hipErrorInvalidValue;  // single-workgroup lengths only
   {
     const int threads = cfg.cols * static_cast<int>(N1 / 8);
     const size_t lds = sizeof(double2) * lpad_size(N1) * cfg.cols;
