@@ -441,6 +441,98 @@ def measure_reach(binding, torch, arithmetic="rect"):
     return out
 
 
+def _median_ms(fn, reps):
+    fn()  # warm-up
+    lat = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        lat.append(time.perf_counter() - t)
+    return float(np.median(lat) * 1e3)
+
+
+def measure_baselines(binding, torch, ns=(64, 256, 1024, 4096, 16384, 65536, 131072), reps=7):
+    """The paper's section 3 comparison on the GPU: one product at a time of two
+    uniform random n-byte operands (seed 60,000 + n), median latency of `reps`
+    calls with the host synchronisation of each call included, for long
+    multiplication (ssa_mul_long), the non-rigorous transforms in double and
+    single precision (the latter while it fits one workgroup) and the rigorous
+    rectangles and discs (ssa_mul).  `exact` says whether the product equals
+    CPython's integer product (the naive transforms can be wrong)."""
+    from paper_1006_0405_amd.workloads import pair
+    out = {}
+    for n in ns:
+        a, b = pair(60_000 + n, n)
+        want = (int.from_bytes(a.tobytes(), "little") *
+                int.from_bytes(b.tobytes(), "little")).to_bytes(2 * n, "little")
+        da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+        res = torch.empty(2 * n, dtype=torch.uint8, device="cuda")
+        row = {"fft_length": binding.fft_size(n, n)}
+        variants = [("long_multiplication", "rect", True), ("naive_fp64", "naive", False),
+                    ("interval_rect", "rect", False), ("interval_disc", "disc", False)]
+        if binding.fft_size(n, n) <= 4096:
+            variants.insert(2, ("naive_fp32", "naive32", False))
+        for name, arith, lm in variants:
+            plan = binding.Plan(n, n, arithmetic=arith)
+            call = (lambda: plan.mul_long(da, db, out=res)) if lm else (lambda: plan.mul(da, db, out=res))
+            ms = _median_ms(call, reps)
+            st, _ = call()
+            row[name] = {"ms": ms, "status": binding.STATUS_NAMES[st],
+                         "exact": res.cpu().numpy().tobytes() == want}
+            plan.close()
+        out[str(n)] = row
+    # section 1: the naive single-precision transform at 120 base-256 digits
+    count = 4096
+    A, B = zip(*[pair(61_000 + i, 120) for i in range(count)])
+    plan = binding.Plan(120, 120, arithmetic="naive32")
+    bt = binding.Batch(plan, list(A), list(B))
+    bt.run()
+    torch.cuda.synchronize()
+    wrong = sum((bt.OUT[i].cpu().numpy().tobytes() !=
+                 (int.from_bytes(A[i].tobytes(), "little") *
+                  int.from_bytes(B[i].tobytes(), "little")).to_bytes(240, "little"))
+                for i in range(count))
+    bt.close()
+    plan.close()
+    out["naive_fp32_120x120_bytes"] = {"products": count, "wrong": wrong,
+                                       "wrong_frac": wrong / count}
+    return out
+
+
+def measure_exact(binding, torch, reps=5):
+    """The exact last resort (number-theoretic transform over Z_p): a random
+    2 MiB x 2 MiB product that every FP64 run refuses (the rectangles' radius
+    is about 4 at N = 2^22), timed through ssa_mul of an exact_fallback plan
+    (the refused interval run plus the exact run), and 4 MiB x 4 MiB products
+    (N = 2^24, beyond the interval kernels: the exact run only).  Products are
+    checked against CPython's integers (2 MiB) and by residues modulo a 61-bit
+    prime (4 MiB)."""
+    from paper_1006_0405_amd.workloads import pair
+    out = {}
+    for n, name, full in ((1 << 21, "2MiB_random_fp64_refused", True),
+                          (1 << 22, "4MiB_random_beyond_2p22", False)):
+        a, b = pair(62_000 + n, n)
+        plan = binding.Plan(n, n, exact_fallback=True)
+        da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+        res = torch.empty(2 * n, dtype=torch.uint8, device="cuda")
+        ms = _median_ms(lambda: plan.mul(da, db, out=res), reps)
+        st, _ = plan.mul(da, db, out=res)
+        s = plan.stats()
+        z = res.cpu().numpy().tobytes()
+        A, B = int.from_bytes(a.tobytes(), "little"), int.from_bytes(b.tobytes(), "little")
+        if full:
+            ok = z == (A * B).to_bytes(2 * n, "little")
+        else:
+            q = 2305843009213693951
+            ok = (A % q) * (B % q) % q == int.from_bytes(z, "little") % q
+        assert st == binding.SSA_OK and s["refined"] == 3 and ok, name
+        out[name] = {"operand_bytes": n, "fft_length": 1 << s["log_n"], "latency_ms": ms,
+                     "status": binding.STATUS_NAMES[st], "refined": s["refined"],
+                     "checked": "integer product" if full else "residue mod 2^61 - 1"}
+        plan.close()
+    return out
+
+
 def measure_arith(binding, torch, A, Bs, steps, warmup, arithmetic):
     """The timed workload (the same operands) in another arithmetic: FP64
     discs ("disc") or the non-rigorous point baseline ("naive"); autotuned
@@ -495,6 +587,10 @@ def main():
                     help="skip the one-at-a-time products (1,024, 75,000 and 1,000,000 bytes)")
     ap.add_argument("--no-disc", action="store_true",
                     help="skip the same workload in FP64 discs and in the naive point baseline")
+    ap.add_argument("--no-baselines", action="store_true",
+                    help="skip the section 3 comparison per operand length (long multiplication, "
+                         "naive double and single precision, rectangles, discs) and the exact "
+                         "last resort")
     ap.add_argument("--no-fft", action="store_true",
                     help="skip the standalone forward interval FFT (64 transforms of 2^18)")
     ap.add_argument("--separate-transforms", action="store_true",
@@ -507,6 +603,9 @@ def main():
     ap.add_argument("--only-fft", action="store_true",
                     help="only the standalone forward interval FFT (64 transforms of 2^18), for "
                          "profiling its two kernels")
+    ap.add_argument("--only-exact", action="store_true",
+                    help="only the exact last resort (number-theoretic transform), for profiling "
+                         "its kernels")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (torch), the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings")
@@ -535,6 +634,10 @@ def main():
         shape = tuple(int(v) for v in args.shape.split(",")) if args.shape else None
         print(json.dumps({"fft_forward_2p18": measure_fft(binding, torch, args.steps, shape=shape)}),
               flush=True)
+        return
+
+    if args.only_exact:
+        print(json.dumps({"exact_rung": measure_exact(binding, torch)}), flush=True)
         return
 
     B = args.batch
@@ -734,6 +837,10 @@ def main():
         r32["speedup_vs_fp64"] = r32["products_per_s"] / r64["products_per_s"]
         result["frontier_100x100_base16_fp64"] = r64
         result["frontier_100x100_base16_fp32_fallback"] = r32
+
+    if not args.no_baselines:
+        result["baselines_per_n"] = measure_baselines(binding, torch)
+        result["exact_rung"] = measure_exact(binding, torch)
 
     if not args.no_cpu_baseline:
         n = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
