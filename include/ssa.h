@@ -170,9 +170,10 @@ size_t ssa_fft_size(size_t na, size_t nb, int digit_bits);
 ssa_status ssa_plan_create(ssa_plan **plan, size_t max_na, size_t max_nb,
                            const ssa_plan_opts *opts, void *stream);
 
-/* Release a plan and everything it allocated (twiddle table, scratch, pinned
- * staging); waits for the plan's stream first.  Batches created from the plan
- * must be destroyed before it.  NULL is ignored. */
+/* Release a plan and everything it allocated (the section 2.2 twiddle table,
+ * scratch, pinned staging; no paper passage beyond that: resource handling);
+ * waits for the plan's stream first.  Batches created from the plan must be
+ * destroyed before it.  NULL is ignored. */
 void ssa_plan_destroy(ssa_plan *plan);
 
 /* z = a * b (section 2, long multiplication box: x in Z_b^n, y in Z_b^m ->
@@ -260,7 +261,8 @@ ssa_status ssa_plan_corrupt_bound(ssa_plan *plan, long long index);
 ssa_status ssa_get_stats(const ssa_plan *plan, ssa_stats *stats_host);
 
 /* Batches: `count` independent products of uneven lengths, each within the
- * plan's max_na / max_nb.  The arrays a, na, b, nb, out are HOST arrays of
+ * plan's max_na / max_nb, each certified on its own (section 1: detection per
+ * instance, so one refused product does not affect the others).  The arrays a, na, b, nb, out are HOST arrays of
  * device pointers and byte counts.  Creation validates every product,
  * allocates the batch's device scratch (the batch owns it), groups the
  * products by transform length, uploads the work descriptors and captures the
@@ -269,10 +271,14 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
                             const size_t *na, const uint8_t *const *b, const size_t *nb,
                             uint8_t *const *out, ssa_batch **batch);
 /* Run a batch (one graph launch, stream-ordered, no host synchronisation).
- * status_dev: device array of `count` ints, receives each product's ssa_status. */
+ * status_dev: device array of `count` ints, receives each product's ssa_status
+ * (section 1: the certified product, or the error for that product alone). */
 ssa_status ssa_batch_run(ssa_batch *batch, int *status_dev);
-/* Per-product statistics of the last run (host array of `count`); synchronises. */
+/* Per-product statistics of the last run (host array of `count`: the section 2.5
+ * enclosure radius and the counts of ssa_stats); synchronises. */
 ssa_status ssa_batch_stats(ssa_batch *batch, ssa_stats *stats_host);
+/* Release a batch and its device scratch and graph (resource handling); NULL is
+ * ignored. */
 void ssa_batch_destroy(ssa_batch *batch);
 
 /* Run a batch without its graph, with a HIP event recorded on the plan's

@@ -249,28 +249,6 @@ __device__ __forceinline__ ci ci_mul_fast(const ci &a, const ci &b) {
                      to_mrad(b.in, b.ih, 1.0));
 }
 
-// Real interval product (paper section 2.5, four end-point products): with
-// x = [-xn, xh], y = [-yn, yh] the end-point products are xn*yn, -xn*yh,
-// -xh*yn, xh*yh; hi = max of them rounded up, nlo = max of their negatives
-// rounded up.
-struct ri {
-  double n, h;
-};
-__device__ __forceinline__ ri ri_mul(double xn, double xh, double yn, double yh) {
-  const double h = dmax(dmax(ru_mul(xn, yn), ru_nmul(xn, yh)), dmax(ru_nmul(xh, yn), ru_mul(xh, yh)));
-  const double n = dmax(dmax(ru_nmul(xn, yn), ru_mul(xn, yh)), dmax(ru_mul(xh, yn), ru_nmul(xh, yh)));
-  return ri{n, h};
-}
-// Complex interval product (paper section 2.5):
-// ([z1][w1] - [z2][w2]) + i([z1][w2] + [z2][w1]).
-__device__ __forceinline__ ci ci_mul(const ci &z, const ci &w) {
-  const ri a = ri_mul(z.rn, z.rh, w.rn, w.rh);  // z1 w1
-  const ri b = ri_mul(z.in, z.ih, w.in, w.ih);  // z2 w2
-  const ri c = ri_mul(z.rn, z.rh, w.in, w.ih);  // z1 w2
-  const ri d = ri_mul(z.in, z.ih, w.rn, w.rh);  // z2 w1
-  return ci{ru_add(a.n, b.h), ru_add(a.h, b.n), ru_add(c.n, d.n), ru_add(c.h, d.h)};
-}
-
 // Multiplication of every bound by 2^-k (exact unless it underflows; rounding
 // up keeps both stored bounds valid either way).
 __device__ __forceinline__ ci ci_scale(const ci &a, double p2) {

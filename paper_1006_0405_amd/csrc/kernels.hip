@@ -775,6 +775,10 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
   const bool self = p == 0;
   const uint32_t k1 = role == 0 ? p : (self ? N1 / 2 : N1 - p);
   constexpr size_t rowslots = lpad_size(size_t(1) << LOG_N2);
+  // rows of at most 2^8 points: the pair's two row groups (2 N2/8 <= 64
+  // threads) are one wavefront, whose LDS operations complete in order, so
+  // the partner exchange needs no workgroup barrier
+  constexpr bool PW = LOG_N2 <= 8;
   double2 *hown = hbuf + static_cast<size_t>(rg) * rowslots;
   double2 *hpart = self ? hown : hbuf + static_cast<size_t>(rg ^ 1) * rowslots;
   const size_t row = static_cast<size_t>(k1) << LOG_N2;
@@ -787,8 +791,8 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
   // their partner's value, and hand it to the partner, whose element lies in
   // the other half (k2 >= N2/2) -- except in row 0, where k2 = N2/2 is its own
   // partner and k2 = 0 is partnered with itself too.  Exchanges go in 16-byte
-  // words through LDS, with workgroup barriers (the partner row may be another
-  // wavefront).
+  // words through LDS, with workgroup barriers when the partner row is another
+  // wavefront.
   uint32_t src[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
@@ -798,19 +802,19 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
   const bool own4 = k1 == 0 && j == 0;  // k2 = N2/2 of row 0: its own partner
   // 1. partner values for r < 4 (and the self-partnered element)
   double2 pr[5];
-  __syncthreads();
+  xsync<PW>();
 #pragma unroll
   for (int r = 0; r < 8; ++r)
     if (r >= 4 || own4) hown[lpad(j + r * M8)] = e_word0(v[r]);
-  __syncthreads();
+  xsync<PW>();
 #pragma unroll
   for (int r = 0; r < 4; ++r) pr[r] = hpart[lpad(src[r])];
   if (own4) pr[4] = hpart[lpad(src[4])];
-  __syncthreads();
+  xsync<PW>();
 #pragma unroll
   for (int r = 0; r < 8; ++r)
     if (r >= 4 || own4) hown[lpad(j + r * M8)] = e_word1(v[r]);
-  __syncthreads();
+  xsync<PW>();
   E C[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -825,22 +829,22 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
   }
   // 2. the products to the partners: element -k receives C_k = conj(C_{-k})
   double2 t0[4];
-  __syncthreads();
+  xsync<PW>();
 #pragma unroll
   for (int r = 0; r < 4; ++r) hpart[lpad(src[r])] = e_word0(C[r]);
-  __syncthreads();
+  xsync<PW>();
 #pragma unroll
   for (int r = 4; r < 8; ++r) t0[r - 4] = hown[lpad(j + r * M8)];
-  __syncthreads();
+  xsync<PW>();
 #pragma unroll
   for (int r = 0; r < 4; ++r) hpart[lpad(src[r])] = e_word1(C[r]);
-  __syncthreads();
+  xsync<PW>();
 #pragma unroll
   for (int r = 4; r < 8; ++r)
     if (r != 4 || !own4) e_from_words(v[r], t0[r - 4], hown[lpad(j + r * M8)]);
 #pragma unroll
   for (int r = 0; r < 4; ++r) v[r] = e_conj(C[r]);
-  __syncthreads();  // the partner has read this row's buffer
+  xsync<PW>();  // the partner has read this row's buffer
   half_inverse_row<LOG_N2, WAVE>(v, j, k1, log_n1, hown, T, T, mr_of(tk.ya, log_n));
 }
 

@@ -18,9 +18,10 @@
 // lv[2^l + u] = w_{2^l}^u, 0 <= u < 2^l, l <= K, of the roots of unity
 // w_{2^l} of order 2^l.  Each transform is a sequence of Stockham passes of
 // radix R in {2, 4, 8, 16} (natural order in and out); a pass gives each
-// thread R elements at stride N / R, multiplies them by w_{R Ns}^{r k}, runs a
-// length-R transform in registers and writes them at stride Ns (the length of
-// the transforms the previous passes completed).  The inverse transform is
+// thread R elements at stride N / R, multiplies them by w_{R Ns}^{r k} (powers
+// of the one table entry w_{R Ns}^k), runs a length-R transform in registers
+// and writes them at stride Ns (the length of the transforms the previous
+// passes completed).  The inverse transform is
 // the forward one read backwards: x_n = N^-1 X'_{-n mod N}, X' the forward
 // transform of X.
 #include <hip/hip_runtime.h>
@@ -159,9 +160,17 @@ __global__ __launch_bounds__(256) void k_ntt_pass(ntt_pass_args p, int log_n, in
       v[r] = p.in[idx];
   }
   if (Ns > 1) {
-    const uint64_t *tw = lv + (static_cast<size_t>(R) << log_ns);  // level R Ns
+    // w_{R Ns}^{r k} as powers of one entry of level R Ns: one load per thread,
+    // contiguous over the lanes (strided reads of w^{r k} for every r would
+    // touch up to R times the cache lines of the whole level)
+    const uint64_t w1 = lv[(static_cast<size_t>(R) << log_ns) + k];
+    uint64_t wr = w1;
+    v[1] = mp_mul(v[1], w1);
 #pragma unroll
-    for (int r = 1; r < R; ++r) v[r] = mp_mul(v[r], tw[r * k]);
+    for (int r = 2; r < R; ++r) {
+      wr = mp_mul(wr, w1);
+      v[r] = mp_mul(v[r], wr);
+    }
   }
   uint64_t w[R / 2];
 #pragma unroll

@@ -269,3 +269,22 @@ def test_fp64_digit_bits_arguments():
             binding.Plan(100, 100, fp64_digit_bits=8, **kw)
     with pytest.raises(binding.SsaError):
         binding.Plan(100, 100, digit_bits=4, precision="fp32_fallback", fp64_digit_bits=4)
+
+
+def test_autotune_with_fp64_digit_bits_tunes_the_length_the_batch_runs():
+    """A base-16 plan that sends long products to FP64 with base-256 digits
+    tunes the base-256 length those products run at (8192-byte operands:
+    N = 2^14), installs the chosen shape for it, and its batch runs there."""
+    plan = binding.Plan(8192, 8192, digit_bits=4, precision="fp32_fallback", fp64_digit_bits=8)
+    res = plan.autotune(14, count=4)
+    got = plan.get_config(14)
+    assert all(got[k] == res[k] for k in got), (got, res)
+    A, B = zip(*[pair(8_000 + i, 8192) for i in range(4)])
+    bt = binding.Batch(plan, list(A), list(B))
+    st = _np(bt.run())
+    assert np.all(st == binding.SSA_OK)
+    assert all(s["log_n"] == 14 for s in bt.stats())
+    for i in range(4):
+        assert np.array_equal(_np(bt.OUT[i]), int_product(A[i], B[i])), i
+    bt.close()
+    plan.close()
