@@ -207,6 +207,10 @@ struct ssa_batch {
   size_t n_multi = 0;
   uint2 *d_tile_map = nullptr;  // (task slot, tile) per carry workgroup
   uint32_t total_tiles = 0;
+  // the same tiles as two maps, the first halves' products then the second
+  // halves' (graph form: each half's carries run on its own stream)
+  uint2 *d_tile_map_split = nullptr;
+  uint32_t tiles_a = 0, tiles_b = 0;
   // timed (eager) runs: one event before and one after every kernel launch
   std::vector<hipEvent_t> events;
   std::vector<int> kinds;
@@ -673,6 +677,7 @@ ssa_status ssa_probe_directed(int op, const double *a, const double *b, const do
 
 void ssa_batch_destroy(ssa_batch *bt) {
   if (!bt) return;
+  (void)hipFree(bt->d_tile_map_split);
   if (bt->plan) (void)hipStreamSynchronize(bt->plan->stream);
   for (hipEvent_t ev : bt->events) (void)hipEventDestroy(ev);
   if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
@@ -736,13 +741,20 @@ hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk,
     }
     s0 = s1;
   }
+  // one digit size for every multi-pass product (the FP32 attempt is single-workgroup)
   if (split) {
-    hipError_t e = hipEventRecord(join, side);
+    // each half's carries on its stream, so that one half's latency-bound
+    // carry scan overlaps the other half's passes
+    hipError_t e = hipSuccess;
+    if (bt->tiles_a)
+      e = launch_carry_map(bt->d_tasks, bt->d_tile_map_split, bt->tiles_a, bt->bits[0], s, hk);
+    if (e == hipSuccess && bt->tiles_b)
+      e = launch_carry_map(bt->d_tasks, bt->d_tile_map_split + bt->tiles_a, bt->tiles_b,
+                           bt->bits[0], side, hk);
+    if (e == hipSuccess) e = hipEventRecord(join, side);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
     if (e != hipSuccess) return e;
-  }
-  if (bt->n_multi) {
-    // one digit size for every multi-pass product (the FP32 attempt is single-workgroup)
+  } else if (bt->n_multi) {
     hipError_t e = launch_carry_map(bt->d_tasks, bt->d_tile_map, bt->total_tiles, bt->bits[0], s, hk);
     if (e != hipSuccess) return e;
   }
@@ -883,8 +895,31 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
     for (size_t k = bt->n_multi; k-- > 0;)
       for (uint32_t t = 0; t < bt->h_tasks[k].ntiles; ++t) map.push_back(make_uint2(static_cast<uint32_t>(k), t));
     bt->total_tiles = static_cast<uint32_t>(map.size());
-    ok = !map.empty() && hip_ok(hipMalloc(&bt->d_tile_map, sizeof(uint2) * map.size())) &&
+    // the halves of every multi-pass class as the graph splits them (classes
+    // of two or more products: the first n/2 slots, then the rest)
+    std::vector<char> in_b(bt->n_multi, 0);
+    for (size_t s0 = 0; s0 < bt->n_multi;) {
+      size_t s1 = s0;
+      while (s1 < bt->n_multi && bt->h_tasks[s1].log_n == bt->h_tasks[s0].log_n &&
+             bt->bits[s1] == bt->bits[s0])
+        ++s1;
+      if (s1 - s0 >= 2)
+        for (size_t k = s0 + (s1 - s0) / 2; k < s1; ++k) in_b[k] = 1;
+      s0 = s1;
+    }
+    std::vector<uint2> split_map;
+    for (int half = 0; half < 2; ++half)
+      for (size_t k = bt->n_multi; k-- > 0;)
+        if (in_b[k] == half)
+          for (uint32_t t = 0; t < bt->h_tasks[k].ntiles; ++t)
+            split_map.push_back(make_uint2(static_cast<uint32_t>(k), t));
+    for (size_t k = 0; k < bt->n_multi; ++k) (in_b[k] ? bt->tiles_b : bt->tiles_a) += bt->h_tasks[k].ntiles;
+    ok = !map.empty() && split_map.size() == map.size() &&
+         hip_ok(hipMalloc(&bt->d_tile_map, sizeof(uint2) * map.size())) &&
+         hip_ok(hipMalloc(&bt->d_tile_map_split, sizeof(uint2) * map.size())) &&
          hip_ok(hipMemcpyAsync(bt->d_tile_map, map.data(), sizeof(uint2) * map.size(),
+                               hipMemcpyHostToDevice, st)) &&
+         hip_ok(hipMemcpyAsync(bt->d_tile_map_split, split_map.data(), sizeof(uint2) * map.size(),
                                hipMemcpyHostToDevice, st)) &&
          hip_ok(hipStreamSynchronize(st));
     if (!ok) {
