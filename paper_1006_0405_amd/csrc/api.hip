@@ -153,6 +153,23 @@ ssa_stats to_public(const dev_stats &s, int log_n) {
 
 bool kernels_configured = false;
 
+// Concurrent branches of a batch graph: each multi-pass class is split into
+// this many parts, one per stream, each part followed by its own carry scan.
+// Two measured fastest: 64 products of 75,000 bytes take 0.414 ms per graph
+// launch with two branches, 0.439 ms with four (and 0.434 ms with two branches
+// whose carries waited for both).
+constexpr int GRAPH_BRANCHES = 2;
+static_assert(GRAPH_BRANCHES >= 1 && GRAPH_BRANCHES <= 8, "graph branches: 1..8 streams");
+
+// Part of a class of n products (slots s0 .. s0 + n) that slot k belongs to when
+// the class is split into `parts` (part q: slots s0 + q n / parts onwards).
+int part_of(size_t k, size_t s0, size_t n, int parts) {
+  const size_t off = k - s0;
+  int q = 0;
+  while (q + 1 < parts && off >= (q + 1) * n / parts) ++q;
+  return q;
+}
+
 }  // namespace
 
 struct ssa_plan {
@@ -163,7 +180,8 @@ struct ssa_plan {
   int hooks = 0;         // test hooks (HOOK_FORCE_FP32_FAIL)
   int force_too_wide = 0;  // test hook: certification refuses every coefficient
   int corrupt_index = -1;  // test hook: coefficient whose upper bound is lowered by 1 (-1: off)
-  int split_graph = 1;     // batch graphs run each multi-pass class as two concurrent halves
+  int split_graph = GRAPH_BRANCHES;  // batch graphs run each multi-pass class as this many
+                                     // concurrent parts (1: one stream)
   size_t max_na = 0, max_nb = 0;
   int log_nmax = 0;
   int log_nref = 0;  // refine_digits: largest base-16 re-run transform (0: none)
@@ -207,10 +225,10 @@ struct ssa_batch {
   size_t n_multi = 0;
   uint2 *d_tile_map = nullptr;  // (task slot, tile) per carry workgroup
   uint32_t total_tiles = 0;
-  // the same tiles as two maps, the first halves' products then the second
-  // halves' (graph form: each half's carries run on its own stream)
+  // the same tiles grouped by graph branch (graph form: each branch's carries
+  // run on its own stream), branch 0's products first
   uint2 *d_tile_map_split = nullptr;
-  uint32_t tiles_a = 0, tiles_b = 0;
+  uint32_t branch_tiles[8] = {};
   // timed (eager) runs: one event before and one after every kernel launch
   std::vector<hipEvent_t> events;
   std::vector<int> kinds;
@@ -706,20 +724,23 @@ namespace {
 
 // Per length class one launch (or three), then one carry scan over every
 // multi-pass product, then the statuses.
-// side (graph capture only): a second stream; each multi-pass class is then
-// split in two halves, the second half launched on `side` between a fork and a
-// join event, so that the two halves' kernels can share the GPU (one half's
-// memory phases overlap the other's arithmetic).
+// side (graph capture only): nside more streams; each multi-pass class is then
+// split into up to nside + 1 parts, part q launched on stream q (stream 0 is
+// s) between a fork and a join event, so that the parts' kernels can share the
+// GPU (one part's memory phases and latency-bound carries overlap another's
+// arithmetic); each stream ends with the carry scan of its own products.
 hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk,
-                         hipStream_t side = nullptr, hipEvent_t fork = nullptr,
-                         hipEvent_t join = nullptr) {
+                         hipStream_t *side = nullptr, int nside = 0, hipEvent_t fork = nullptr,
+                         hipEvent_t *join = nullptr) {
   const ssa_plan *p = bt->plan;
   size_t s0 = 0;
   const size_t count = bt->count;
-  const bool split = side != nullptr && bt->n_multi >= 2;
+  const bool split = side != nullptr && nside > 0 && bt->n_multi >= 2;
+  const int branches = split ? nside + 1 : 1;
+  const auto stream_of = [&](int q) { return q == 0 ? s : side[q - 1]; };
   if (split) {
     hipError_t e = hipEventRecord(fork, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    for (int q = 0; q < nside && e == hipSuccess; ++q) e = hipStreamWaitEvent(side[q], fork, 0);
     if (e != hipSuccess) return e;
   }
   while (s0 < count) {
@@ -730,11 +751,14 @@ hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk,
     int n32 = 0;
     while (n32 < n && bt->h_tasks[s0 + n32].fp32) ++n32;  // marked tasks lead their class
     if (split && l > SMALL_MAX_LOG && n >= 2) {
-      const int h = n / 2;
-      hipError_t e = enqueue_class(p, bt->d_tasks + s0, h, 0, l, nullptr, s, hk, cb);
-      if (e == hipSuccess)
-        e = enqueue_class(p, bt->d_tasks + s0 + h, n - h, 0, l, nullptr, side, hk, cb);
-      if (e != hipSuccess) return e;
+      const int parts = std::min(branches, n);
+      for (int q = 0; q < parts; ++q) {
+        const int b0 = static_cast<int>(size_t(q) * n / parts);
+        const int b1 = static_cast<int>(size_t(q + 1) * n / parts);
+        const hipError_t e =
+            enqueue_class(p, bt->d_tasks + s0 + b0, b1 - b0, 0, l, nullptr, stream_of(q), hk, cb);
+        if (e != hipSuccess) return e;
+      }
     } else {
       const hipError_t e = enqueue_class(p, bt->d_tasks + s0, n, n32, l, nullptr, s, hk, cb);
       if (e != hipSuccess) return e;
@@ -743,16 +767,18 @@ hipError_t enqueue_batch(ssa_batch *bt, hipStream_t s, const timing_hook *hk,
   }
   // one digit size for every multi-pass product (the FP32 attempt is single-workgroup)
   if (split) {
-    // each half's carries on its stream, so that one half's latency-bound
-    // carry scan overlaps the other half's passes
     hipError_t e = hipSuccess;
-    if (bt->tiles_a)
-      e = launch_carry_map(bt->d_tasks, bt->d_tile_map_split, bt->tiles_a, bt->bits[0], s, hk);
-    if (e == hipSuccess && bt->tiles_b)
-      e = launch_carry_map(bt->d_tasks, bt->d_tile_map_split + bt->tiles_a, bt->tiles_b,
-                           bt->bits[0], side, hk);
-    if (e == hipSuccess) e = hipEventRecord(join, side);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+    uint32_t off = 0;
+    for (int q = 0; q < branches && e == hipSuccess; ++q) {
+      if (bt->branch_tiles[q])
+        e = launch_carry_map(bt->d_tasks, bt->d_tile_map_split + off, bt->branch_tiles[q],
+                             bt->bits[0], stream_of(q), hk);
+      off += bt->branch_tiles[q];
+    }
+    for (int q = 0; q < nside && e == hipSuccess; ++q) {
+      e = hipEventRecord(join[q], side[q]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, join[q], 0);
+    }
     if (e != hipSuccess) return e;
   } else if (bt->n_multi) {
     hipError_t e = launch_carry_map(bt->d_tasks, bt->d_tile_map, bt->total_tiles, bt->bits[0], s, hk);
@@ -895,25 +921,30 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
     for (size_t k = bt->n_multi; k-- > 0;)
       for (uint32_t t = 0; t < bt->h_tasks[k].ntiles; ++t) map.push_back(make_uint2(static_cast<uint32_t>(k), t));
     bt->total_tiles = static_cast<uint32_t>(map.size());
-    // the halves of every multi-pass class as the graph splits them (classes
-    // of two or more products: the first n/2 slots, then the rest)
-    std::vector<char> in_b(bt->n_multi, 0);
+    // the parts of every multi-pass class as the graph splits them (a class of
+    // n >= 2 products into min(branches, n) parts), so that each branch's
+    // carries cover its own products
+    const int branches = plan->split_graph;
+    std::vector<int> branch(bt->n_multi, 0);
     for (size_t s0 = 0; s0 < bt->n_multi;) {
       size_t s1 = s0;
       while (s1 < bt->n_multi && bt->h_tasks[s1].log_n == bt->h_tasks[s0].log_n &&
              bt->bits[s1] == bt->bits[s0])
         ++s1;
-      if (s1 - s0 >= 2)
-        for (size_t k = s0 + (s1 - s0) / 2; k < s1; ++k) in_b[k] = 1;
+      const size_t n = s1 - s0;
+      if (branches > 1 && n >= 2)
+        for (size_t k = s0; k < s1; ++k)
+          branch[k] = part_of(k, s0, n, std::min<int>(branches, static_cast<int>(n)));
       s0 = s1;
     }
     std::vector<uint2> split_map;
-    for (int half = 0; half < 2; ++half)
+    for (int q = 0; q < branches; ++q)
       for (size_t k = bt->n_multi; k-- > 0;)
-        if (in_b[k] == half)
+        if (branch[k] == q) {
           for (uint32_t t = 0; t < bt->h_tasks[k].ntiles; ++t)
             split_map.push_back(make_uint2(static_cast<uint32_t>(k), t));
-    for (size_t k = 0; k < bt->n_multi; ++k) (in_b[k] ? bt->tiles_b : bt->tiles_a) += bt->h_tasks[k].ntiles;
+          bt->branch_tiles[q] += bt->h_tasks[k].ntiles;
+        }
     ok = !map.empty() && split_map.size() == map.size() &&
          hip_ok(hipMalloc(&bt->d_tile_map, sizeof(uint2) * map.size())) &&
          hip_ok(hipMalloc(&bt->d_tile_map_split, sizeof(uint2) * map.size())) &&
@@ -929,14 +960,16 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
     }
   }
   // Capture the launch sequence into one graph.
-  hipStream_t cs = nullptr, side = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  const int nside = plan->split_graph - 1;
+  hipStream_t cs = nullptr, side[7] = {};
+  hipEvent_t fork = nullptr, join[7] = {};
   ok = hip_ok(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) &&
-       hip_ok(hipStreamCreateWithFlags(&side, hipStreamNonBlocking)) &&
-       hip_ok(hipEventCreateWithFlags(&fork, hipEventDisableTiming)) &&
-       hip_ok(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+       hip_ok(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  for (int q = 0; q < nside && ok; ++q)
+    ok = hip_ok(hipStreamCreateWithFlags(&side[q], hipStreamNonBlocking)) &&
+         hip_ok(hipEventCreateWithFlags(&join[q], hipEventDisableTiming));
   if (ok) ok = hip_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  if (ok) ok = hip_ok(enqueue_batch(bt, cs, nullptr, plan->split_graph ? side : nullptr, fork, join));
+  if (ok) ok = hip_ok(enqueue_batch(bt, cs, nullptr, nside > 0 ? side : nullptr, nside, fork, join));
   hipGraph_t g = nullptr;
   if (cs) {
     const hipError_t ec = hipStreamEndCapture(cs, &g);
@@ -949,9 +982,11 @@ ssa_status ssa_batch_create(ssa_plan *plan, size_t count, const uint8_t *const *
     (void)hipGraphDestroy(g);
   }
   if (cs) (void)hipStreamDestroy(cs);
-  if (side) (void)hipStreamDestroy(side);
+  for (int q = 0; q < nside; ++q) {
+    if (side[q]) (void)hipStreamDestroy(side[q]);
+    if (join[q]) (void)hipEventDestroy(join[q]);
+  }
   if (fork) (void)hipEventDestroy(fork);
-  if (join) (void)hipEventDestroy(join);
   if (!ok) {
     ssa_batch_destroy(bt);
     (void)hipGetLastError();

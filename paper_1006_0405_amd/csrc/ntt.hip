@@ -125,25 +125,47 @@ struct ntt_pass_args {
   uint64_t ninv;        // DST_COEFFS: N^-1 mod p
 };
 
+// The product's statistics and carry state, reset by its first pass (block 0).
+__device__ __forceinline__ void reset_product(const task &tk) {
+  if (threadIdx.x == 0) {
+    tk.st->max_rad_bits = 0ull;
+    tk.st->half_int = 0ull;
+    tk.st->too_wide = 0u;
+    tk.st->internal = 0u;
+    tk.st->carry_err = 0u;
+    tk.st->fallback = 0u;
+    tk.st->fp32 = 0u;
+  }
+  for (uint32_t t = threadIdx.x; t < tk.ntiles; t += blockDim.x) tk.tiles[t * TILE_WORD_STRIDE] = 0u;
+}
+
+// Input idx of a pass (SRC) and its output at position pos (DST).
+template <int SRC>
+__device__ __forceinline__ uint64_t ntt_get(const ntt_pass_args &p, uint32_t idx) {
+  if constexpr (SRC == SRC_DIGITS)
+    return idx < p.nd ? static_cast<uint64_t>(p.dig[idx]) : 0ull;
+  else
+    return p.in[idx];
+}
+template <int DST>
+__device__ __forceinline__ void ntt_put(const ntt_pass_args &p, uint32_t N, uint32_t pos, uint64_t v) {
+  if constexpr (DST == DST_ARRAY) {
+    p.out[pos] = v;
+  } else if constexpr (DST == DST_TIMES) {
+    p.out[pos] = mp_mul(v, p.mul[pos]);
+  } else {
+    // inverse: x_n = N^-1 X'_{-n}; the residue is the coefficient itself
+    p.out[(N - pos) & (N - 1)] = mp_mul(v, p.ninv);
+  }
+}
+
 // One Stockham pass of radix R: thread j (< N/R) reads v_r = x[j + r N/R],
 // k = j mod Ns, multiplies by w_{R Ns}^{r k}, transforms, and writes
 // y[(j - k) R + k + r Ns].
 template <int R, int SRC, int DST>
 __global__ __launch_bounds__(256) void k_ntt_pass(ntt_pass_args p, int log_n, int log_ns,
                                                   const uint64_t *lv, const task *tk_reset) {
-  if (tk_reset != nullptr && blockIdx.x == 0) {  // the product's first pass
-    const task tk = *tk_reset;
-    if (threadIdx.x == 0) {
-      tk.st->max_rad_bits = 0ull;
-      tk.st->half_int = 0ull;
-      tk.st->too_wide = 0u;
-      tk.st->internal = 0u;
-      tk.st->carry_err = 0u;
-      tk.st->fallback = 0u;
-      tk.st->fp32 = 0u;
-    }
-    for (uint32_t t = threadIdx.x; t < tk.ntiles; t += blockDim.x) tk.tiles[t * TILE_WORD_STRIDE] = 0u;
-  }
+  if (tk_reset != nullptr && blockIdx.x == 0) reset_product(*tk_reset);  // the first pass
   const uint32_t N = 1u << log_n;
   const uint32_t M = N / R;  // threads of the pass
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -152,13 +174,7 @@ __global__ __launch_bounds__(256) void k_ntt_pass(ntt_pass_args p, int log_n, in
   const uint32_t k = j & (Ns - 1);
   uint64_t v[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t idx = j + r * M;
-    if constexpr (SRC == SRC_DIGITS)
-      v[r] = idx < p.nd ? static_cast<uint64_t>(p.dig[idx]) : 0ull;
-    else
-      v[r] = p.in[idx];
-  }
+  for (int r = 0; r < R; ++r) v[r] = ntt_get<SRC>(p, j + r * M);
   if (Ns > 1) {
     // w_{R Ns}^{r k} as powers of one entry of level R Ns: one load per thread,
     // contiguous over the lanes (strided reads of w^{r k} for every r would
@@ -178,17 +194,87 @@ __global__ __launch_bounds__(256) void k_ntt_pass(ntt_pass_args p, int log_n, in
   dft_r<R, 1>(v, w);
   const uint32_t base = (j - k) * R + k;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t pos = base + r * Ns;
-    if constexpr (DST == DST_ARRAY) {
-      p.out[pos] = v[r];
-    } else if constexpr (DST == DST_TIMES) {
-      p.out[pos] = mp_mul(v[r], p.mul[pos]);
-    } else {
-      // inverse: x_n = N^-1 X'_{-n}; the residue is the coefficient itself
-      p.out[(N - pos) & (N - 1)] = mp_mul(v[r], p.ninv);
+  for (int r = 0; r < R; ++r) ntt_put<DST>(p, N, base + r * Ns, v[r]);
+}
+
+// Fused pass of radix R = Q^2 (Q = 8 or 16): two radix-Q stages of the same
+// Stockham step through LDS, so a transform takes about half the passes over
+// HBM.  With r = r1 + Q r2 and q = q2 + Q q1 the length-R transform is
+//   X_{q2 + Q q1} = sum_{r1} w_Q^{r1 q1} w_R^{r1 q2} sum_{r2} v_{r1 + Q r2} w_Q^{r2 q2}.
+// A workgroup of 256 threads takes C = 256/Q consecutive values of j; thread
+// (jl, a) first holds v_{a + Q r2} (r2 < Q), applies the pass twiddle
+// w_{R Ns}^{(a + Q r2) k} (powers of the one entry w_{R Ns}^k), transforms over
+// r2 and applies w_R^{a q2}; after the exchange it holds the values of its
+// q2 = a for every r1, transforms over r1 and writes X_{a + Q q1} to
+// y[(j - k) R + k + (a + Q q1) Ns].  QFAST (the first pass, Ns = 1: each j's
+// outputs are contiguous) puts a in the fastest lanes so the writes coalesce;
+// otherwise jl is fastest (loads and writes contiguous over j).
+template <int Q, int SRC, int DST, bool QFAST>
+__global__ __launch_bounds__(256) void k_ntt_pass2(ntt_pass_args p, int log_n, int log_ns,
+                                                   const uint64_t *lv, const task *tk_reset) {
+  constexpr int R = Q * Q;
+  constexpr int C = 256 / Q;
+  constexpr int JS = R + 1;  // LDS words per j (one spare word against bank conflicts)
+  __shared__ uint64_t sh[C * JS];
+  if (tk_reset != nullptr && blockIdx.x == 0) reset_product(*tk_reset);
+  const uint32_t N = 1u << log_n;
+  const uint32_t M = N / R;
+  const uint32_t Ns = 1u << log_ns;
+  const int t = threadIdx.x;
+  const int jl = QFAST ? t / Q : t % C;
+  const int a = QFAST ? t % Q : t / C;
+  const uint32_t j = blockIdx.x * C + jl;  // grid = M / C: every j exists
+  const uint32_t k = j & (Ns - 1);
+  uint64_t v[Q];
+#pragma unroll
+  for (int r2 = 0; r2 < Q; ++r2) v[r2] = ntt_get<SRC>(p, j + static_cast<uint32_t>(a + Q * r2) * M);
+  if (Ns > 1) {
+    const uint64_t W = lv[(static_cast<size_t>(R) << log_ns) + k];  // w_{R Ns}^k
+    uint64_t f = 1, WQ = W;
+    for (int b = a, wb = 0; b; b >>= 1, ++wb) {  // f = W^a, a < Q
+      uint64_t x = W;
+      for (int s2 = 0; s2 < wb; ++s2) x = mp_mul(x, x);
+      if (b & 1) f = mp_mul(f, x);
+    }
+#pragma unroll
+    for (int s2 = 1; s2 < Q; s2 <<= 1) WQ = mp_mul(WQ, WQ);  // W^Q
+#pragma unroll
+    for (int r2 = 0; r2 < Q; ++r2) {
+      if (r2 > 0) f = mp_mul(f, WQ);
+      v[r2] = mp_mul(v[r2], f);
     }
   }
+  uint64_t wq[Q / 2];
+#pragma unroll
+  for (int q = 0; q < Q / 2; ++q) wq[q] = lv[Q + q];  // w_Q^q
+  dft_r<Q, 1>(v, wq);
+  if (a > 0) {
+#pragma unroll
+    for (int q2 = 1; q2 < Q; ++q2) v[q2] = mp_mul(v[q2], lv[R + a * q2]);  // w_R^{a q2}
+  }
+#pragma unroll
+  for (int q2 = 0; q2 < Q; ++q2) sh[jl * JS + q2 * Q + a] = v[q2];
+  __syncthreads();
+#pragma unroll
+  for (int r1 = 0; r1 < Q; ++r1) v[r1] = sh[jl * JS + a * Q + r1];
+  dft_r<Q, 1>(v, wq);
+  const uint32_t base = (j - k) * R + k;
+#pragma unroll
+  for (int q1 = 0; q1 < Q; ++q1) ntt_put<DST>(p, N, base + static_cast<uint32_t>(a + Q * q1) * Ns, v[q1]);
+}
+
+template <int SRC, int DST, bool QFAST>
+hipError_t launch_pass2(int Q, const ntt_pass_args &a, int log_n, int log_ns, const uint64_t *lv,
+                        const task *tk_reset, hipStream_t s) {
+  const uint32_t R = static_cast<uint32_t>(Q) * Q, C = 256u / Q;
+  const dim3 grid(((1u << log_n) / R) / C);
+  if (Q == 16)
+    hipLaunchKernelGGL((k_ntt_pass2<16, SRC, DST, QFAST>), grid, dim3(256), 0, s, a, log_n, log_ns,
+                       lv, tk_reset);
+  else
+    hipLaunchKernelGGL((k_ntt_pass2<8, SRC, DST, QFAST>), grid, dim3(256), 0, s, a, log_n, log_ns,
+                       lv, tk_reset);
+  return hipGetLastError();
 }
 
 template <int SRC, int DST>
@@ -213,9 +299,24 @@ hipError_t launch_pass_r(int R, const ntt_pass_args &a, int log_n, int log_ns, c
   return hipGetLastError();
 }
 
-// Radix of pass i of a length-2^log_n transform: 16 while four or more
-// levels remain, then what is left.
-int pass_radix_log(int log_n, int done) { return log_n - done >= 4 ? 4 : log_n - done; }
+// Next pass of a length-2^log_n transform after `done` levels: a fused pass
+// of radix 256 while eight or more levels remain (2^12 points and more: a
+// workgroup takes 16 values of j), then of radix 64 while six remain (2^11
+// points and more), then single passes of radix 16, and what is left.
+// Returns log2 of the radix; *Q is the fused pass's Q (0: a single pass).
+int next_pass(int log_n, int done, int *Q) {
+  const int rem = log_n - done;
+  *Q = 0;
+  if (rem >= 8 && log_n >= 12) {
+    *Q = 16;
+    return 8;
+  }
+  if (rem >= 6 && log_n >= 11) {
+    *Q = 8;
+    return 6;
+  }
+  return rem >= 4 ? 4 : rem;
+}
 
 }  // namespace
 
@@ -238,7 +339,8 @@ static hipError_t transform(const uint8_t *dig, uint32_t nd, const uint64_t *in,
   const uint64_t *src = in;
   uint64_t *dst = (in == b0) ? b1 : b0;
   while (done < log_n) {
-    const int lr = pass_radix_log(log_n, done);
+    int Q = 0;
+    const int lr = next_pass(log_n, done, &Q);
     const int R = 1 << lr;
     const bool first = done == 0, last = done + lr == log_n;
     ntt_pass_args a{};
@@ -250,7 +352,18 @@ static hipError_t transform(const uint8_t *dig, uint32_t nd, const uint64_t *in,
     a.ninv = ninv;
     const task *rs = first ? tk_reset : nullptr;
     hipError_t e;
-    if (first && dig != nullptr) {
+    if (Q != 0) {  // fused (never both the first and the last pass: log_n >= 11)
+      if (first && dig != nullptr) e = launch_pass2<SRC_DIGITS, DST_ARRAY, true>(Q, a, log_n, done, lv, rs, s);
+      else if (first) e = launch_pass2<SRC_ARRAY, DST_ARRAY, true>(Q, a, log_n, done, lv, rs, s);
+      else if (last && coeffs) {
+        a.out = coeffs;
+        e = launch_pass2<SRC_ARRAY, DST_COEFFS, false>(Q, a, log_n, done, lv, rs, s);
+      } else if (last && mul) {
+        e = launch_pass2<SRC_ARRAY, DST_TIMES, false>(Q, a, log_n, done, lv, rs, s);
+      } else {
+        e = launch_pass2<SRC_ARRAY, DST_ARRAY, false>(Q, a, log_n, done, lv, rs, s);
+      }
+    } else if (first && dig != nullptr) {
       if (last && mul) e = launch_pass_r<SRC_DIGITS, DST_TIMES>(R, a, log_n, done, lv, rs, s);
       else e = launch_pass_r<SRC_DIGITS, DST_ARRAY>(R, a, log_n, done, lv, rs, s);
     } else if (last && coeffs) {
