@@ -126,7 +126,7 @@ __device__ __forceinline__ void exchange8(E v[8], int j, int M8, double2 *h, int
 // half-element exchange buffer; element i lives at h[lpad(i) << lis].  With
 // WAVE the group must be exactly the lanes of (part of) one wavefront;
 // otherwise every thread of the workgroup must call this with the same M.
-template <int LOGM, bool WAVE, bool PF = false, class TT = twtab, class E = ci>
+template <int LOGM, bool WAVE, bool PF = false, class TT = twtab, class E = ci, bool LAZY = false>
 __device__ __forceinline__ void fft8_group(E v[8], int j, double2 *h, int lis, const TT &T) {
   static_assert(LOGM >= 3, "length-8 groups at least");
   constexpr int M8 = 1 << (LOGM - 3);
@@ -136,7 +136,9 @@ __device__ __forceinline__ void fft8_group(E v[8], int j, double2 *h, int lis, c
   const double c8 = w8.x, e8 = T.e;  // |1/sqrt 2 - c8| <= e
   // PF: twiddles of the next radix-8 stage are loaded one stage ahead, so that
   // their latency overlaps the current stage's arithmetic and exchange (at the
-  // cost of 28 more live registers); otherwise they are loaded where used.
+  // cost of 28 more live registers); otherwise a stage's seven twiddles are
+  // loaded together at its start, or with LAZY each right before its product
+  // (the fewest live registers).
   double2 w[8];
   const auto load_tw = [&](int lns) {
     const int k = j & ((1 << lns) - 1);
@@ -176,8 +178,17 @@ __device__ __forceinline__ void fft8_group(E v[8], int j, double2 *h, int lis, c
     const int logNs = FIRST + 3 * st;
     const int Ns = 1 << logNs;
     const int k = j & (Ns - 1);
-    if (!PF && logNs > 0) load_tw(logNs);
-    if (logNs > 0) {
+    if (!PF && !LAZY && logNs > 0) load_tw(logNs);
+    if (LAZY && logNs > 0) {
+      // each twiddle loaded where it is used: fewer live registers
+#pragma unroll
+      for (int r = 1; r < 8; ++r) {
+        const double2 wr = root(T, logNs + 3, static_cast<uint32_t>(r * k));
+        v[r] = r <= 2 ? e_tw_q1(v[r], wr.x, wr.y, T.e)
+             : r <= 4 ? e_tw_uh(v[r], wr.x, wr.y, T.e)
+                      : e_tw(v[r], wr.x, wr.y, T.e);
+      }
+    } else if (logNs > 0) {
       // omega_{8 Ns}^{r k} with k < Ns has angle below r pi / 4: for r <= 2 the
       // root lies in the first quadrant, for r <= 4 in the upper half plane,
       // and so do the stored points (rounded to nearest from the same side)

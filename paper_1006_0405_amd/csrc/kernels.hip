@@ -27,6 +27,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "fft8.hpp"
 #include "mr32.hpp"
@@ -961,8 +962,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
 // column n2 < N2/2 gives y_{n2 + (N2/2) n1} = x_{2 m} + i x_{2 m + 1} with
 // 2 m = N2 n1 + 2 n2, and each part is certified as one coefficient.
 // grid = (N2 / 2 / C, tasks).
+// Rectangles, columns of 2^7 points and more: each stage twiddle loaded right
+// where it is used, which keeps the kernel at 124-126 registers (four waves
+// per SIMD, no spills): 6.5% faster than three waves at 136 registers with a
+// stage's twiddles loaded together (64 products at 2^18).  Discs measured
+// slower that way and keep the default; at 2^6 the cap would spill.
 template <int LOG_N1, class E>
-__global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n2, int lc, int mode,
+__global__ __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(std::is_same<E, ci>::value && LOG_N1 >= 7 ? 4 : 2)))
+void k_col_inv(const task *tasks, int log_n2, int lc, int mode,
                                                  twtab T, double *dbg) {
   extern __shared__ double2 hbuf[];
   __shared__ cert_shared sh;
@@ -980,7 +988,7 @@ __global__ __launch_bounds__(512) void k_col_inv(const task *tasks, int log_n2, 
     const uint32_t k1 = j + r * M8;
     v[r] = e_conj(mr_load<E>(mr_of(tk.ya, log_n), (static_cast<size_t>(k1) << log_n2) + n2));
   }
-  fft8_group<LOG_N1, false>(v, j, hbuf + c, lc, T);
+  fft8_group<LOG_N1, false, false, twtab, E, std::is_same<E, ci>::value>(v, j, hbuf + c, lc, T);
   const double scale = ldexp(1.0, -log_n);
   cert_acc acc{0.0, 0u, 0u, 0u};
 #pragma unroll
