@@ -790,62 +790,60 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
   // Each pair {k, -k} of the two rows needs one product: C_{-k} = conj(C_k)
   // (the coefficients are real).  Elements k2 < N2/2 (r < 4) compute it from
   // their partner's value, and hand it to the partner, whose element lies in
-  // the other half (k2 >= N2/2) -- except in row 0, where k2 = N2/2 is its own
-  // partner and k2 = 0 is partnered with itself too.  Exchanges go in 16-byte
-  // words through LDS, with workgroup barriers when the partner row is another
-  // wavefront.
-  uint32_t src[8];
+  // the other half (k2 >= N2/2) -- except in row 0, where k2 = 0 and k2 = N2/2
+  // are their own partners (both held by thread 0).  The exchange goes through
+  // the row buffers, free once the row DFT is done: each row's elements
+  // k2 >= N2/2 sit at slot w N2/2 + (k2 - N2/2) for their two 16-byte words w
+  // (k2 = 0 of row 0 at the spare slots N2, N2 + 1).  Every slot is read by one
+  // thread only (the partner of its element), and that thread writes the
+  // product back into the very slot it read, so the exchange needs just two
+  // barriers when the partner row is another wavefront: after the values are
+  // written, and after the products are.
+  constexpr uint32_t H2 = N2 / 2;
+  constexpr bool TWO = e_traits<E>::words == 2;
+  const bool own4 = k1 == 0 && j == 0;
+  int ps[4];  // slot of Z_{-k} for r < 4 (in the partner's buffer)
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
+  for (int r = 0; r < 4; ++r) {
     const uint32_t k2 = j + r * M8;
-    src[r] = k1 == 0 ? ((N2 - k2) & (N2 - 1)) : (N2 - 1 - k2);
+    const uint32_t m = k1 == 0 ? ((N2 - k2) & (N2 - 1)) : (N2 - 1 - k2);  // -k's column
+    ps[r] = r == 0 && own4 ? static_cast<int>(N2) : static_cast<int>(m - H2);
   }
-  const bool own4 = k1 == 0 && j == 0;  // k2 = N2/2 of row 0: its own partner
-  // 1. partner values for r < 4 (and the self-partnered element)
-  double2 pr[5];
-  xsync<PW>();
+  // k2 = N2/2 of row 0 is its own partner: its final value, computed here,
+  // goes out and comes back unchanged (no thread reads its slot as a partner)
+  if (own4) v[4] = e_conj(separated_product(v[4], e_conj(v[4])));
+  if constexpr (!WAVE) xsync<false>();  // the row's other waves are done with the DFT's exchanges
 #pragma unroll
-  for (int r = 0; r < 8; ++r)
-    if (r >= 4 || own4) hown[lpad(j + r * M8)] = e_word0(v[r]);
-  xsync<PW>();
-#pragma unroll
-  for (int r = 0; r < 4; ++r) pr[r] = hpart[lpad(src[r])];
-  if (own4) pr[4] = hpart[lpad(src[4])];
-  xsync<PW>();
-#pragma unroll
-  for (int r = 0; r < 8; ++r)
-    if (r >= 4 || own4) hown[lpad(j + r * M8)] = e_word1(v[r]);
+  for (int r = 4; r < 8; ++r) {
+    const int e = j + (r - 4) * M8;
+    hown[e] = e_word0(v[r]);
+    if constexpr (TWO) hown[H2 + e] = e_word1(v[r]);
+  }
+  if (own4) {
+    hown[N2] = e_word0(v[0]);
+    if constexpr (TWO) hown[N2 + 1] = e_word1(v[0]);
+  }
   xsync<PW>();
   E C[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
+    const int w1 = ps[r] == static_cast<int>(N2) ? static_cast<int>(N2 + 1) : static_cast<int>(H2) + ps[r];
     E Zm;  // Z_{-k}
-    e_from_words(Zm, pr[r], hpart[lpad(src[r])]);
+    e_from_words(Zm, hpart[ps[r]], TWO ? hpart[w1] : make_double2(0.0, 0.0));
     C[r] = separated_product(v[r], e_conj(Zm));
+    // element -k receives conj(C_{-k}) = C_k, in the slot its value came from
+    hpart[ps[r]] = e_word0(C[r]);
+    if constexpr (TWO) hpart[w1] = e_word1(C[r]);
   }
-  if (own4) {
-    E Zm;
-    e_from_words(Zm, pr[4], hpart[lpad(src[4])]);
-    v[4] = e_conj(separated_product(v[4], e_conj(Zm)));
+  xsync<PW>();
+#pragma unroll
+  for (int r = 4; r < 8; ++r) {
+    const int e = j + (r - 4) * M8;
+    e_from_words(v[r], hown[e], TWO ? hown[H2 + e] : make_double2(0.0, 0.0));
   }
-  // 2. the products to the partners: element -k receives C_k = conj(C_{-k})
-  double2 t0[4];
-  xsync<PW>();
-#pragma unroll
-  for (int r = 0; r < 4; ++r) hpart[lpad(src[r])] = e_word0(C[r]);
-  xsync<PW>();
-#pragma unroll
-  for (int r = 4; r < 8; ++r) t0[r - 4] = hown[lpad(j + r * M8)];
-  xsync<PW>();
-#pragma unroll
-  for (int r = 0; r < 4; ++r) hpart[lpad(src[r])] = e_word1(C[r]);
-  xsync<PW>();
-#pragma unroll
-  for (int r = 4; r < 8; ++r)
-    if (r != 4 || !own4) e_from_words(v[r], t0[r - 4], hown[lpad(j + r * M8)]);
 #pragma unroll
   for (int r = 0; r < 4; ++r) v[r] = e_conj(C[r]);
-  xsync<PW>();  // the partner has read this row's buffer
+  // (the row DFT of the inverse synchronises before its first write to hown)
   half_inverse_row<LOG_N2, WAVE>(v, j, k1, log_n1, hown, T, T, mr_of(tk.ya, log_n));
 }
 

@@ -25,7 +25,7 @@ NBYTES = 4096
 def test_class_of_more_than_65535_products():
     print("%d products of %d x %d bytes in one length class" % (COUNT, NBYTES, NBYTES), flush=True)
     a, b = pair(65_000, NBYTES)
-    want = torch.from_numpy(int_product(a, b)).cuda()
+    want = torch.from_numpy(int_product(a, b).copy()).cuda()
     da = torch.from_numpy(a).cuda()
     db = torch.from_numpy(b).cuda()
     out = torch.zeros((COUNT, 2 * NBYTES), dtype=torch.uint8, device="cuda")
