@@ -234,13 +234,23 @@ __device__ __forceinline__ void exchange4(E v[4], int j, int M4, double2 *h, W w
 // threads: thread j holds x[j + r M/4], r < 4, and ends with X[j + q M/4].
 // Stockham radix-4 stages (one radix-2 stage first when LOGM is odd), same
 // conventions as fft8_group; the twiddles omega_{4 Ns}^{r k}, k < Ns, lie in
-// the first quadrant for r = 1, the upper half plane for r = 2.
+// the first quadrant for r = 1, the upper half plane for r = 2.  A stage's
+// three twiddles are loaded before the exchange that precedes it, so that
+// their latency overlaps the exchange.
 template <int LOGM, bool WAVE, class TT = twtab, class E = ci>
 __device__ __forceinline__ void fft4_group(E v[4], int j, double2 *h, const TT &T) {
   static_assert(LOGM >= 2, "length-4 groups at least");
   constexpr int M4 = 1 << (LOGM - 2);
   constexpr int FIRST = LOGM % 2;
   constexpr int NR4 = (LOGM - FIRST) / 2;
+  double2 w1, w2, w3;
+  const auto load_tw = [&](int lns) {
+    const int kk = j & ((1 << lns) - 1);
+    w1 = root(T, lns + 2, static_cast<uint32_t>(kk));
+    w2 = root(T, lns + 2, static_cast<uint32_t>(2 * kk));
+    w3 = root(T, lns + 2, static_cast<uint32_t>(3 * kk));
+  };
+  if (FIRST == 1) load_tw(1);
   if (FIRST == 1) {
     // radix 2 (Ns = 1): positions jv = j + t M/4 (t < 2) pair x[jv] = v_t with
     // x[jv + M/2] = v_{t+2}; results to y[2 jv], y[2 jv + 1]
@@ -260,15 +270,13 @@ __device__ __forceinline__ void fft4_group(E v[4], int j, double2 *h, const TT &
     const int Ns = 1 << logNs;
     const int k = j & (Ns - 1);
     if (logNs > 0) {
-      const double2 w1 = root(T, logNs + 2, static_cast<uint32_t>(k));
-      const double2 w2 = root(T, logNs + 2, static_cast<uint32_t>(2 * k));
-      const double2 w3 = root(T, logNs + 2, static_cast<uint32_t>(3 * k));
       v[1] = e_tw_q1(v[1], w1.x, w1.y, T.e);
       v[2] = e_tw_uh(v[2], w2.x, w2.y, T.e);
       v[3] = e_tw(v[3], w3.x, w3.y, T.e);
     }
     radix4(v);
     if (st + 1 == NR4) break;  // X[j + q M/4] = v[q]
+    load_tw(logNs + 2);
     const int base = ((j - k) << 2) + k;
     exchange4<WAVE>(v, j, M4, h, [&](int q) { return base + q * Ns; });
   }

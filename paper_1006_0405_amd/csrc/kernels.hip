@@ -618,11 +618,11 @@ __device__ __forceinline__ void mr_store(const mrbuf &b, size_t idx, const pt &v
 // as the forward DFT of the conjugate, so the rows work on P = conj Z_k and
 // Q = conj Z_{k+N/2}:  conj U_k = (P + Q) - i omega_N^k (P - Q).  An enclosure
 // of y is one of x: its real part encloses x_{2m} and its imaginary part
-// x_{2m+1}, because the exact x is real.
+// x_{2m+1}, because the exact x is real.  w is omega_N^k as a point within
+// ew of the root; k < N/2 puts it in the upper half plane (see apply_pass_tw).
 template <class E>
-__device__ __forceinline__ E half_inverse_input(const E &P, const E &Q, const twtab &T, uint32_t k,
-                                                int log_n) {
-  const E t = apply_pass_tw<true>(e_sub(P, Q), T, k, 1u, log_n);  // k < N/2
+__device__ __forceinline__ E half_inverse_input(const E &P, const E &Q, double2 w, double ew) {
+  const E t = e_tw_uh(e_sub(P, Q), w.x, w.y, ew);
   return e_add(e_add(P, Q), e_mul_negi(t));
 }
 
@@ -638,11 +638,17 @@ __device__ __forceinline__ void half_inverse_row(const E v[8], int j, uint32_t k
                                                  const mrbuf &Y) {
   constexpr int M8 = 1 << (LOG_N2 - 3);
   const int log_n = log_n1 + LOG_N2;
+  // omega_N^k for k = k1 + N1 k2 is omega_N^{k1} omega_{N2}^{k2}, two table
+  // entries (the bound pass_tw_bound covers their product); the first is the
+  // same for the whole row, a scalar load when the row is whole wavefronts
+  const uint32_t k1u = M8 >= 64 ? __builtin_amdgcn_readfirstlane(k1) : k1;
+  const double2 w1 = root(T, log_n, k1u);
   E u[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
-    u[r] = half_inverse_input(v[r], v[r + 4], T, k1 + (static_cast<uint32_t>(j + r * M8) << log_n1),
-                              log_n);
+    u[r] = half_inverse_input(v[r], v[r + 4],
+                              tw_point_product(w1, root(T, LOG_N2, static_cast<uint32_t>(j + r * M8))),
+                              pass_tw_bound(T.e));
   fft4_group<LOG_N2 - 1, WAVE>(u, j, h, TF);
 #pragma unroll
   for (int q = 0; q < 4; ++q) u[q] = e_conj(apply_pass_tw(u[q], T, j + q * M8, k1, log_n - 1));
@@ -786,7 +792,7 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
   E v[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) v[r] = mr_load<E>(mr_of(tk.ya, log_n), row + j + r * M8);
-  fft8_group<LOG_N2, WAVE, (LOG_N2 > 9)>(v, j, hown, 0, T);  // twiddle prefetch for long rows
+  fft8_group<LOG_N2, WAVE, true>(v, j, hown, 0, T);  // stage twiddles loaded a stage ahead
   // Each pair {k, -k} of the two rows needs one product: C_{-k} = conj(C_k)
   // (the coefficients are real).  Elements k2 < N2/2 (r < 4) compute it from
   // their partner's value, and hand it to the partner, whose element lies in
@@ -848,10 +854,9 @@ __device__ __forceinline__ void row_pair_body(const task &tk, int log_n1, int G,
 }
 
 template <int LOG_N2, class E>
-// Rows of up to 2^9 points: four waves per SIMD (registers capped at 128, a few
-// values spill) without the twiddle prefetch of the row DFT, 4% faster at
-// N = 2^18 than three waves with it.  Longer rows: three waves (168 registers)
-// with the prefetch, which measured faster than two.
+// Rows of up to 2^9 points: four waves per SIMD (registers capped at 128, no
+// spills), the stage twiddles of both row DFTs loaded a stage ahead.  Longer
+// rows: three waves (168 registers), which measured faster than two.
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(LOG_N2 <= 9 ? 4 : 3))) void k_row_pair(const task *tasks, int log_n1, int G, twtab T) {
   extern __shared__ double2 hbuf[];
   const uint32_t z = enter_mode<E>();
