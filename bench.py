@@ -579,7 +579,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=64, help="products per step")
+    ap.add_argument("--batch", type=int, default=256, help="products per step (one graph launch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 4096-product uneven batch (FP64 base 256 and base 16)")
