@@ -116,6 +116,18 @@ __device__ __forceinline__ double dmax(double a, double b) {
   asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
   return r;
 }
+// Positive and negative parts max(a, 0) and max(-a, 0) (exact; the negation is
+// a source modifier and 0 an inline constant).
+__device__ __forceinline__ double dpos(double a) {
+  double r;
+  asm("v_max_f64 %0, %1, 0" : "=v"(r) : "v"(a));
+  return r;
+}
+__device__ __forceinline__ double dneg(double a) {
+  double r;
+  asm("v_max_f64 %0, -%1, 0" : "=v"(r) : "v"(a));
+  return r;
+}
 __device__ __forceinline__ double dfloor(double a) {
   double r;
   asm("v_floor_f64 %0, %1" : "=v"(r) : "v"(a));
@@ -162,8 +174,8 @@ __device__ __forceinline__ ci ci_conj(const ci &a) { return ci{a.rn, a.rh, a.ih,
 // rectangular product [w][z] (section 2.5) with the twiddle's rounding error
 // folded into a common radius term.
 __device__ __forceinline__ ci ci_twiddle(const ci &z, double c, double s, double e) {
-  const double cp = dmax(c, 0.0), cn = dmax(-c, 0.0);
-  const double sp = dmax(s, 0.0), sn = dmax(-s, 0.0);
+  const double cp = dpos(c), cn = dneg(c);
+  const double sp = dpos(s), sn = dneg(s);
   const double mx = dmax(z.rn, z.rh), my = dmax(z.in, z.ih);
   const double E = ru_mul(e, ru_add(mx, my));
   ci r;
@@ -190,7 +202,7 @@ __device__ __forceinline__ ci ci_twiddle_q1(const ci &z, double c, double s, dou
   return r;
 }
 __device__ __forceinline__ ci ci_twiddle_uh(const ci &z, double c, double s, double e) {
-  const double cp = dmax(c, 0.0), cn = dmax(-c, 0.0);
+  const double cp = dpos(c), cn = dneg(c);
   const double mx = dmax(z.rn, z.rh), my = dmax(z.in, z.ih);
   const double E = ru_mul(e, ru_add(mx, my));
   ci r;
