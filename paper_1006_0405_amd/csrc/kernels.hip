@@ -651,7 +651,9 @@ __device__ __forceinline__ void half_inverse_row(const E v[8], int j, uint32_t k
                               pass_tw_bound(T.e));
   fft4_group<LOG_N2 - 1, WAVE>(u, j, h, TF);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) u[q] = e_conj(apply_pass_tw(u[q], T, j + q * M8, k1, log_n - 1));
+  for (int q = 0; q < 4; ++q)  // n2 k1 < N/4 for q < 2: the upper half plane
+    u[q] = e_conj(q < 2 ? apply_pass_tw<true>(u[q], T, j + q * M8, k1, log_n - 1)
+                        : apply_pass_tw(u[q], T, j + q * M8, k1, log_n - 1));
   stores_after_loads();
   const size_t row = static_cast<size_t>(k1) << LOG_N2;
 #pragma unroll
@@ -1065,7 +1067,9 @@ __global__ __launch_bounds__(512) void k_fft_col(const double *x, double *y, int
   for (int r = 0; r < 8; ++r) v[r] = load_public(x, base + (static_cast<size_t>(j + r * M8) << log_n2) + n2);
   fft8_group<LOG_N1, false>(v, j, hbuf + c, lc, T);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) v[q] = apply_pass_tw(v[q], T, n2, j + q * M8, log_n);
+  for (int q = 0; q < 8; ++q)  // n2 k1 < N/2 for q < 4: the upper half plane
+    v[q] = q < 4 ? apply_pass_tw<true>(v[q], T, n2, j + q * M8, log_n)
+                 : apply_pass_tw(v[q], T, n2, j + q * M8, log_n);
   stores_after_loads();
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
