@@ -354,7 +354,7 @@ __device__ __forceinline__ void small_body(const task &tk, int bits, int mode, i
         mr_to_e(w[r], va[r]);
       }
     } else {
-      fft8_group<LOG_N, WAVE>(va, j, h, 0, T);
+      fft8_group<LOG_N, WAVE, false, twtab, E, false, true>(va, j, h, 0, T);  // thin digits
     }
     // One product per pair {k, -k} (C_{-k} = conj C_k, the coefficients are
     // real): k < N/2 (r < 4) computes it from Z_{-k} and hands it to element
@@ -430,8 +430,8 @@ __device__ __forceinline__ void small_body(const task &tk, int bits, int mode, i
 #pragma unroll
       for (int r = 0; r < 8; ++r) vb[r] = mr_to_ci(w[r]);
     } else {
-      fft8_group<LOG_N, WAVE>(va, j, h, 0, T);
-      fft8_group<LOG_N, WAVE>(vb, j, h, 0, T);
+      fft8_group<LOG_N, WAVE, false, twtab, ci, false, true>(va, j, h, 0, T);  // thin digits
+      fft8_group<LOG_N, WAVE, false, twtab, ci, false, true>(vb, j, h, 0, T);
     }
 #pragma unroll
     for (int r = 0; r < 8; ++r) va[r] = ci_conj(ci_mul_fast(va[r], vb[r]));
@@ -720,7 +720,7 @@ __global__ __launch_bounds__(512) void k_col_fwd(const task *tasks, int log_n2, 
       v[r] = ci_thin_real(digit_value(ra[r], nd, idx[r], bits));
     }
   }
-  fft8_group<LOG_N1, false>(v, j, hbuf + c, lc, T);
+  fft8_group<LOG_N1, false, false, twtab, E, false, true>(v, j, hbuf + c, lc, T);  // thin digits
   const mrbuf Y = mr_of(opb ? tk.yb : tk.ya, log_n);
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = apply_pass_tw(v[q], T, n2, j + q * M8, log_n);
