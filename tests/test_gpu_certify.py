@@ -28,9 +28,9 @@ pytestmark = pytest.mark.gpu
 OK, WIDE, INTERNAL = 0, 1, 5
 
 # (re_lo, re_hi), expected outcome, coefficient, half-integer inside.  The first
-# six rows are the certification table of the survey's oracle specification
-# (section 1's rule on closed intervals); the rest add the negative, tail and
-# mixed cases.
+# six rows are the basic cases of section 1's rule on closed intervals (one
+# integer inside, an exact integer, zero, a half-integer end point, two
+# integers, none); the rest add the negative, tail and mixed cases.
 TABLE = [
     ((2.6, 3.4), OK, 3, 0),
     ((3.0, 3.0), OK, 3, 0),
