@@ -72,6 +72,28 @@ def _cpu_worker(args):
     return st, time.perf_counter() - t0, rad
 
 
+def measure_stream(torch, reps=10):
+    """What HBM gives a plain streaming kernel on this GPU, as a reference for
+    the roofline fractions (which stay against the 8 TB/s peak): torch.add over
+    2^28 float32 values, 1 GiB read and 1 GiB written per launch, timed with
+    HIP events on torch's stream."""
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.add(x, 1.0, out=y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.add(x, 1.0, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbps = 2 * (1 << 30) / (ms * 1e-3) / 1e9
+    del x, y
+    return {"kernel": "torch.add(x, 1, out=y) over 2^28 float32 (1 GiB read, 1 GiB written)",
+            "ms": ms, "GBps": gbps, "frac_of_peak": gbps / HBM_PEAK_GBPS}
+
+
 def cpu_model():
     """The host CPU's model name (from /proc/cpuinfo), or None."""
     try:
@@ -761,6 +783,7 @@ def main():
             "alg_bytes_per_launch": bytes_launch,
             "ms_per_launch": per_launch_ms[dom],
         },
+        "hbm_stream_reference": None,
         "digits_per_s": value * 2 * NBYTES,
         "alg_GBps_whole_step": step_bytes / (elapsed / args.steps) / 1e9,
         "kernel_ms_per_launch": per_launch_ms,
@@ -773,6 +796,9 @@ def main():
     }
     batch.close()
     plan.close()
+    stream = measure_stream(torch)
+    stream["roofline_kernel_frac_of_stream"] = achieved / stream["GBps"]
+    result["hbm_stream_reference"] = stream
     if not args.no_disc:
         d = measure_arith(binding, torch, A, Bs, args.steps, args.warmup, "disc")
         d["speedup_vs_rect"] = d["products_per_s"] / value
