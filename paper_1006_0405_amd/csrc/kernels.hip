@@ -640,7 +640,8 @@ __device__ __forceinline__ void half_inverse_row(const E v[8], int j, uint32_t k
   const int log_n = log_n1 + LOG_N2;
   // omega_N^k for k = k1 + N1 k2 is omega_N^{k1} omega_{N2}^{k2}, two table
   // entries (the bound pass_tw_bound covers their product); the first is the
-  // same for the whole row, a scalar load when the row is whole wavefronts
+  // same for the whole row (one address for the wavefront when the row is
+  // whole wavefronts)
   const uint32_t k1u = M8 >= 64 ? __builtin_amdgcn_readfirstlane(k1) : k1;
   const double2 w1 = root(T, log_n, k1u);
   E u[4];
