@@ -222,6 +222,7 @@ def test_config2_random_and_all_ff(separate):
     assert ost == oracle.ST_OK and np.array_equal(out, oout)
     print("config2 random (%s): GPU max radius %.4f, oracle %.4f"
           % ("separate" if separate else "packed", rad, orad))
+    assert 0 < rad <= orad  # radix-8 stages round less often than the oracle's radix-2 ones
     f = all_ff(n)
     st, out = plan.mul(f, f)
     assert st == binding.SSA_OK
